@@ -1,0 +1,320 @@
+/*
+ * de_oracle.c -- TEST INFRASTRUCTURE, not part of the product.
+ *
+ * A plain, slow, scalar FP64 reference of DE/rand/1/bin as defined in
+ * Janssen, Pullan & Liew, "GPU Based Differential Evolution: New Insights and
+ * Comparative Study" (arXiv 2405.16551), Section 2 (eqs. 2 and 3 and the
+ * selection rule stated with them), with the benchmark transform of
+ * Section 7.3.1 (shift y = x - o, rotation z = M y, search box [-100, 100]).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this file.  It shares no code with the GPU library: the Philox
+ * generator, the index sampler and every piece of arithmetic below are
+ * written here independently.
+ *
+ * Readings of points the paper leaves open (each one is listed in the design
+ * notes of the repository):
+ *   - random numbers come from Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC'11), one stream per
+ *     (tag, run, generation, individual, dimension group);
+ *   - rand_j of eq. 3 lives on the 24-bit lattice {k * 2^-24}; the test
+ *     rand_j <= CR is done exactly in integers;
+ *   - the three mutually exclusive donors of eq. 2 come from a
+ *     rejection-free "skip" map over uniform integers;
+ *   - a mutant coordinate outside the box is clamped back onto it;
+ *   - selection keeps the target on ties (strict "better") and on NaN;
+ *   - generations are synchronous: every donor comes from generation g.
+ *
+ * Precision: every floating-point step is FP64 (the paper fixes none).
+ * Summation runs in index order j = 0 .. D-1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon et al., SC'11): a 4x32-bit counter, a 2x32-bit key,
+ * ten rounds of two 32x32->64 multiplies, key bumped by the Weyl constants
+ * (golden ratio and sqrt(3)-1, as 32-bit fractions) between rounds.        */
+#define OR_PHILOX_M0 0xD2511F53u
+#define OR_PHILOX_M1 0xCD9E8D57u
+#define OR_PHILOX_W0 0x9E3779B9u
+#define OR_PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                          uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += OR_PHILOX_W0;
+      k1 += OR_PHILOX_W1;
+    }
+    uint64_t p0 = (uint64_t)OR_PHILOX_M0 * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)OR_PHILOX_M1 * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Batch form for the tests: n counters/keys laid out [n][4] and [n][2]. */
+void oracle_philox_batch(const uint32_t* ctr, const uint32_t* key,
+                         uint32_t* out, int64_t n) {
+  for (int64_t t = 0; t < n; ++t)
+    oracle_philox4x32_10(ctr + 4 * t, key + 2 * t, out + 4 * t);
+}
+
+enum { OR_TAG_INIT = 1, OR_TAG_IDX = 2, OR_TAG_XOVER = 3 };
+
+/* The four words drawn for (tag, run, gen, individual i, group q).
+ * key = the 64-bit seed split into two words; counter = (q, i, gen,
+ * tag << 24 | run).                                                       */
+static void or_draw(uint64_t seed, int tag, uint32_t run, uint32_t gen,
+                    uint32_t i, uint32_t q, uint32_t w[4]) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {q, i, gen, ((uint32_t)tag << 24) | run};
+  oracle_philox4x32_10(ctr, key, w);
+}
+
+/* Uniform integer in [0, n): the high word of w * n (multiply-shift). */
+uint32_t oracle_uniform_index(uint32_t w, uint32_t n) {
+  return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Mutually exclusive donors for eq. 2: r1, r2, r3 all distinct and all
+ * different from the target i.  a, b, c are uniform in [0, NP-1),
+ * [0, NP-2), [0, NP-3).  Each value is mapped onto the integers of [0, NP)
+ * that are not yet taken by stepping over the taken ones in ascending
+ * order, which is a bijection between the (a, b, c) box and the ordered
+ * triples of distinct indices other than i.                               */
+static int or_skip(int v, const int* taken, int ntaken) {
+  /* taken[] must be sorted ascending */
+  for (int t = 0; t < ntaken; ++t)
+    if (v >= taken[t]) ++v;
+  return v;
+}
+
+static void or_sort(int* a, int n) {
+  for (int s = 1; s < n; ++s)
+    for (int t = s; t > 0 && a[t - 1] > a[t]; --t) {
+      int tmp = a[t]; a[t] = a[t - 1]; a[t - 1] = tmp;
+    }
+}
+
+void oracle_skip_triple(int i, int a, int b, int c, int32_t out[3]) {
+  int taken[3];
+  taken[0] = i;
+  int r1 = or_skip(a, taken, 1);
+  taken[1] = r1;
+  or_sort(taken, 2);
+  int r2 = or_skip(b, taken, 2);
+  taken[2] = r2;
+  or_sort(taken, 3);
+  int r3 = or_skip(c, taken, 3);
+  out[0] = r1; out[1] = r2; out[2] = r3;
+}
+
+/* r1, r2, r3 and j_rand of individual i in generation gen (eqs. 2, 3). */
+void oracle_draw_indices(uint64_t seed, int run, int64_t gen, int i, int NP,
+                         int D, int32_t out[4]) {
+  uint32_t w[4];
+  or_draw(seed, OR_TAG_IDX, (uint32_t)run, (uint32_t)gen, (uint32_t)i, 0u, w);
+  int a = (int)oracle_uniform_index(w[0], (uint32_t)(NP - 1));
+  int b = (int)oracle_uniform_index(w[1], (uint32_t)(NP - 2));
+  int c = (int)oracle_uniform_index(w[2], (uint32_t)(NP - 3));
+  oracle_skip_triple(i, a, b, c, out);
+  out[3] = (int32_t)oracle_uniform_index(w[3], (uint32_t)D);
+}
+
+/* Threshold for "rand_j <= CR" on the 24-bit lattice rand_j = k * 2^-24:
+ * k * 2^-24 <= CR  <=>  k <= floor(CR * 2^24).  CR * 2^24 is exact.      */
+static uint32_t or_cr_threshold(double CR) {
+  return (uint32_t)floor(CR * 16777216.0);
+}
+
+/* Does the trial take the mutant's coordinate j (eq. 3)? */
+int oracle_take_mutant(uint64_t seed, int run, int64_t gen, int i, int j,
+                       int jrand, double CR) {
+  if (j == jrand) return 1;
+  uint32_t w[4];
+  or_draw(seed, OR_TAG_XOVER, (uint32_t)run, (uint32_t)gen, (uint32_t)i,
+          (uint32_t)(j >> 2), w);
+  uint32_t k = w[j & 3] >> 8;
+  return k <= or_cr_threshold(CR);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Objectives of Section 7.3.1: y = x - o; sphere f = sum y_j^2; rotated
+ * oscillating f = sum_i z_i^2 + sin^2(3 z_i) with z = R y, R row-major
+ * [D][D] (z_i = sum_j R[i][j] y_j).                                        */
+enum { OR_OBJ_SPHERE = 0, OR_OBJ_ROT_OSC = 1 };
+
+double oracle_objective(int kind, int D, const double* x, const double* o,
+                        const double* R) {
+  if (kind == OR_OBJ_SPHERE) {
+    double f = 0.0;
+    for (int j = 0; j < D; ++j) {
+      double y = x[j] - o[j];
+      f += y * y;
+    }
+    return f;
+  }
+  double f = 0.0;
+  for (int r = 0; r < D; ++r) {
+    double z = 0.0;
+    for (int j = 0; j < D; ++j) z += R[(size_t)r * D + j] * (x[j] - o[j]);
+    double s = sin(3.0 * z);
+    f += z * z + s * s;
+  }
+  return f;
+}
+
+void oracle_objective_batch(int kind, int D, int64_t n, const double* x,
+                            const double* o, const double* R, double* f,
+                            int nthreads) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int64_t t = 0; t < n; ++t)
+    f[t] = oracle_objective(kind, D, x + t * D, o, R);
+  (void)nthreads;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Population initialisation (Section 2): x_ij uniform in the box,
+ * x_ij = lo + u (hi - lo) with u = k * 2^-24 from the INIT stream, then
+ * every individual is evaluated.  pop is [runs][NP][D].                   */
+void oracle_init(int runs, int NP, int D, double lo, double hi, uint64_t seed,
+                 double* pop) {
+  for (int r = 0; r < runs; ++r)
+    for (int i = 0; i < NP; ++i)
+      for (int j = 0; j < D; ++j) {
+        uint32_t w[4];
+        or_draw(seed, OR_TAG_INIT, (uint32_t)r, 0u, (uint32_t)i,
+                (uint32_t)(j >> 2), w);
+        double u = (double)(w[j & 3] >> 8) * (1.0 / 16777216.0);
+        pop[((size_t)r * NP + i) * D + j] = lo + u * (hi - lo);
+      }
+}
+
+/* ---------------------------------------------------------------------- */
+/* One synchronous generation g -> g+1 of DE/rand/1/bin.
+ *   mutation   (eq. 2): v = x_r1 + F (x_r2 - x_r3), then clamped to [lo, hi]
+ *   crossover  (eq. 3): u_j = v_j if rand_j <= CR or j = j_rand, else x_ij
+ *   selection  (Sec. 2): u replaces x iff f(u) < f(x)
+ * pop/fit hold generation g; pop_next/fit_next receive g+1.  Optional
+ * outputs (NULL to skip): trial [runs][NP][D], ftrial [runs][NP],
+ * accept [runs][NP], draws [runs][NP][4].                                  */
+void oracle_generation(int runs, int NP, int D, double F, double CR, double lo,
+                       double hi, uint64_t seed, int64_t gen, int kind,
+                       const double* o, const double* R, const double* pop,
+                       const double* fit, double* pop_next, double* fit_next,
+                       double* trial, double* ftrial, int32_t* accept,
+                       int32_t* draws, int nthreads) {
+  int64_t total = (int64_t)runs * NP;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int64_t t = 0; t < total; ++t) {
+    int r = (int)(t / NP), i = (int)(t % NP);
+    const double* P = pop + (size_t)r * NP * D;
+    int32_t d[4];
+    oracle_draw_indices(seed, r, gen, i, NP, D, d);
+    const double* x = P + (size_t)i * D;
+    const double* x1 = P + (size_t)d[0] * D;
+    const double* x2 = P + (size_t)d[1] * D;
+    const double* x3 = P + (size_t)d[2] * D;
+    double* u = (double*)malloc(sizeof(double) * (size_t)D);
+    for (int j = 0; j < D; ++j) {
+      if (oracle_take_mutant(seed, r, gen, i, j, d[3], CR)) {
+        double v = x1[j] + F * (x2[j] - x3[j]);
+        if (v < lo) v = lo;
+        if (v > hi) v = hi;
+        u[j] = v;
+      } else {
+        u[j] = x[j];
+      }
+    }
+    double fu = oracle_objective(kind, D, u, o, R);
+    double fx = fit[t];
+    int acc = fu < fx;
+    double* xn = pop_next + (size_t)t * D;
+    memcpy(xn, acc ? u : x, sizeof(double) * (size_t)D);
+    fit_next[t] = acc ? fu : fx;
+    if (trial) memcpy(trial + (size_t)t * D, u, sizeof(double) * (size_t)D);
+    if (ftrial) ftrial[t] = fu;
+    if (accept) accept[t] = acc;
+    if (draws) memcpy(draws + 4 * t, d, sizeof(d));
+    free(u);
+  }
+  (void)nthreads;
+}
+
+/* ---------------------------------------------------------------------- */
+/* A whole run (Section 2 loop; Section 7.3.4 bookkeeping): initialise,
+ * evaluate, then G generations.  Records per run the best value after each
+ * generation (best_trace [runs][G+1], entry 0 = after initialisation), the
+ * first generation whose best is <= target (hit_gen [runs], -1 if never),
+ * and the number of accepted trials (accepted [runs]).  pop_out/fit_out
+ * (nullable) receive the final population.                                */
+int oracle_run(int runs, int NP, int D, double F, double CR, double lo,
+               double hi, uint64_t seed, int kind, const double* o,
+               const double* R, int64_t G, double target, double* best_trace,
+               int64_t* hit_gen, int64_t* accepted, double* pop_out,
+               double* fit_out, int nthreads) {
+  size_t n = (size_t)runs * NP;
+  double* pa = (double*)malloc(sizeof(double) * n * D);
+  double* pb = (double*)malloc(sizeof(double) * n * D);
+  double* fa = (double*)malloc(sizeof(double) * n);
+  double* fb = (double*)malloc(sizeof(double) * n);
+  int32_t* acc = (int32_t*)malloc(sizeof(int32_t) * n);
+  if (!pa || !pb || !fa || !fb || !acc) {
+    free(pa); free(pb); free(fa); free(fb); free(acc);
+    return 1;
+  }
+  oracle_init(runs, NP, D, lo, hi, seed, pa);
+  oracle_objective_batch(kind, D, (int64_t)n, pa, o, R, fa, nthreads);
+  for (int r = 0; r < runs; ++r) {
+    hit_gen[r] = -1;
+    accepted[r] = 0;
+  }
+  for (int64_t g = 0; g <= G; ++g) {
+    if (g > 0) {
+      oracle_generation(runs, NP, D, F, CR, lo, hi, seed, g - 1, kind, o, R,
+                        pa, fa, pb, fb, NULL, NULL, acc, NULL, nthreads);
+      double* t = pa; pa = pb; pb = t;
+      t = fa; fa = fb; fb = t;
+      for (size_t k = 0; k < n; ++k) accepted[k / NP] += acc[k];
+    }
+    for (int r = 0; r < runs; ++r) {
+      double best = fa[(size_t)r * NP];
+      for (int i = 1; i < NP; ++i)
+        if (fa[(size_t)r * NP + i] < best) best = fa[(size_t)r * NP + i];
+      if (best_trace) best_trace[(size_t)r * (G + 1) + g] = best;
+      if (hit_gen[r] < 0 && best <= target) hit_gen[r] = g;
+    }
+  }
+  if (pop_out) memcpy(pop_out, pa, sizeof(double) * n * D);
+  if (fit_out) memcpy(fit_out, fa, sizeof(double) * n);
+  free(pa); free(pb); free(fa); free(fb); free(acc);
+  return 0;
+}
+
+/* Threads the OpenMP runtime would give a parallel region (1 without it). */
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,51 @@
+"""Seeded synthetic objective instances (shift vector o, rotation matrix R).
+
+Section 7.3.1 of Janssen, Pullan & Liew (arXiv 2405.16551) defines every
+benchmark function on the box [-100, 100]^D, shifted by a vector o whose
+entries lie in [-80, 80], then rotated, z = M (x - o).  The paper takes o
+and M from the CEC'14/'17 data files; those are not available, so this
+module draws stand-ins of the same shape and distribution from a seed:
+
+* o ~ U[-80, 80]^D, rounded to FP32 (so x = o, f = 0 is reachable in FP32);
+* R Haar-distributed orthogonal: Q of the QR factorisation of a D x D
+  standard Gaussian matrix, with column signs fixed by sign(diag(R_qr)),
+  rounded to FP32.
+
+The module holds none of the DE arithmetic; it only produces input data,
+fed identically to the FP64 oracle and to the GPU library.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SHIFT_LO = -80.0
+SHIFT_HI = 80.0
+
+
+def _rng(obj_seed: int, D: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(obj_seed),
+                                                         int(D), stream]))
+
+
+def make_shift(D: int, obj_seed: int = 1) -> np.ndarray:
+    """o ~ U[-80, 80]^D as float32."""
+    return _rng(obj_seed, D, 0).uniform(SHIFT_LO, SHIFT_HI, size=D).astype(
+        np.float32)
+
+
+def make_rotation(D: int, obj_seed: int = 1) -> np.ndarray:
+    """Haar-random orthogonal D x D matrix (row-major, z = R y) as float32."""
+    g = _rng(obj_seed, D, 1).standard_normal((D, D))
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diag(r))[None, :]
+    return np.ascontiguousarray(q.astype(np.float32))
+
+
+def make_instance(kind: str, D: int, obj_seed: int = 1):
+    """kind 'sphere' -> (o, None); 'rot_osc' -> (o, R)."""
+    o = make_shift(D, obj_seed)
+    if kind == "sphere":
+        return o, None
+    if kind == "rot_osc":
+        return o, make_rotation(D, obj_seed)
+    raise ValueError(f"unknown objective kind {kind!r}")
