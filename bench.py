@@ -1,0 +1,224 @@
+"""Throughput of the DE/rand/1/bin generation step on one MI355X.
+
+Workload (default): 16 independent runs, NP = 1024, D = 1000, rotated
+oscillating objective z = R (x - o), f = sum z^2 + sin^2(3z), rotation
+product in BF16 on MFMA with FP32 accumulation, F = 0.5, CR = 0.9, search
+box [-100, 100]; synthetic instance (seeded shift and Haar rotation).  One
+step = one synchronous generation of all 16 x 1024 trials (draws, mutation,
+crossover, fitness, selection, write of the next generation).
+
+Prints one JSON line.  value = trial evaluations per second over the timed
+steps (inputs resident in HBM).  Also reported: generations per second,
+the roofline position of the generation kernel (HIP events around every
+launch, algorithmic FLOPs 2 D^2 per trial), a separable companion workload
+(shifted sphere, same sizes; HBM roofline), wall time to the 1e-8 target
+on the small sphere workload (Section 7.3.4 early stopping), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 (matrix and vector)
+
+WORKLOADS = {
+    "rot1000_bf16": dict(runs=16, NP=1024, D=1000, kind="rot_osc",
+                         gemm_prec="bf16"),
+    "rot1000_fp32": dict(runs=16, NP=1024, D=1000, kind="rot_osc",
+                         gemm_prec="fp32"),
+    "sphere1000": dict(runs=16, NP=1024, D=1000, kind="sphere",
+                       gemm_prec="fp32"),
+    "sphere1000_r64": dict(runs=64, NP=1024, D=1000, kind="sphere",
+                           gemm_prec="fp32"),
+    "rot100_r64": dict(runs=64, NP=256, D=100, kind="rot_osc",
+                       gemm_prec="fp32"),
+    "sphere10": dict(runs=1, NP=64, D=10, kind="sphere", gemm_prec="fp32"),
+}
+
+
+def describe(name):
+    w = WORKLOADS[name]
+    obj = ("shifted sphere" if w["kind"] == "sphere" else
+           f"rotated oscillating, {w['gemm_prec']} rotation product")
+    return (f"DE/rand/1/bin, {w['runs']} runs x NP={w['NP']}, D={w['D']}, "
+            f"{obj}, F=0.5, CR=0.9")
+
+
+def algorithmic(w, trials):
+    """Algorithmic work of one generation launch: FLOPs of the rotation
+    product (2 D^2 per trial) or HBM bytes of the separable step (read the
+    target row, write the next row: 8 D + 8 bytes per trial)."""
+    D = w["D"]
+    if w["kind"] == "rot_osc":
+        return 2.0 * D * D * trials, "TFLOP/s"
+    return (8.0 * D + 8.0) * trials, "GB/s"
+
+
+def time_workload(name, steps, warmup, seed=1):
+    import torch
+
+    from paper_2405_16551_amd import instances
+    from paper_2405_16551_amd.de import DifferentialEvolution
+
+    w = WORKLOADS[name]
+    o, R = instances.make_instance(w["kind"], w["D"], 1)
+    de = DifferentialEvolution(runs=w["runs"], NP=w["NP"], D=w["D"], F=0.5,
+                               CR=0.9, seed=seed, kind=w["kind"], o=o, R=R,
+                               gemm_prec=w["gemm_prec"])
+    stream = de.stream
+    de.generation(warmup)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        de.generation(1)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
+    trials = w["runs"] * w["NP"]
+    work, unit = algorithmic(w, trials)
+    if unit == "TFLOP/s":
+        achieved = work / (kern_ms * 1e-3) / 1e12
+        peak = BF16_PEAK_TFLOPS if w["gemm_prec"] == "bf16" else FP32_PEAK_TFLOPS
+        bound = "mfma"
+    else:
+        achieved = work / (kern_ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
+        bound = "hbm"
+    _, best = de.stats()
+    de.close()
+    return dict(wall_s=wall, ms_per_step=wall / steps * 1e3,
+                kernel_ms=kern_ms, evals_per_s=trials * steps / wall,
+                gens_per_s=steps / wall,
+                roofline=dict(bound=bound, achieved=round(achieved, 3),
+                              peak=peak, unit=unit,
+                              frac=round(achieved / peak, 4), traffic=None),
+                best_median=float(sorted(best)[len(best) // 2]))
+
+
+def time_to_target(target=1e-8, max_gens=5000, check_every=50):
+    import torch
+
+    from paper_2405_16551_amd import instances
+    from paper_2405_16551_amd.de import DifferentialEvolution
+
+    o, _ = instances.make_instance("sphere", 10, 1)
+    de = DifferentialEvolution(runs=1, NP=64, D=10, F=0.5, CR=0.9, seed=1,
+                               kind="sphere", o=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, hits = de.evolve(max_gens, target=target, check_every=check_every)
+    t = time.perf_counter() - t0
+    de.close()
+    return dict(workload=describe("sphere10"), target=target, seconds=t,
+                first_hit_generation=hits[0], generations_run=done,
+                check_every=check_every)
+
+
+def cpu_baseline(name, budget_s=15.0):
+    """The FP64 oracle on the host cores, one generation of one run of the
+    workload (NP trials), repeated while the budget lasts."""
+    import numpy as np
+
+    import oracle
+    from paper_2405_16551_amd import instances
+
+    w = WORKLOADS[name]
+    D, NP = w["D"], w["NP"]
+    kind = oracle.OBJ_SPHERE if w["kind"] == "sphere" else oracle.OBJ_ROT_OSC
+    o, R = instances.make_instance(w["kind"], D, 1)
+    threads = oracle.max_threads()
+    pop = oracle.init_population(1, NP, D, -100.0, 100.0, 1)
+    fit = oracle.objective_batch(kind, pop.reshape(-1, D), o, R,
+                                 nthreads=threads).reshape(1, NP)
+    gens, t0 = 0, time.perf_counter()
+    while True:
+        out = oracle.generation(pop, fit, F=0.5, CR=0.9, lo=-100.0, hi=100.0,
+                                seed=1, gen=gens, kind=kind, o=o, R=R,
+                                nthreads=threads)
+        pop, fit = out["pop_next"], out["fit_next"]
+        gens += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or gens >= 10000:
+            break
+    assert np.isfinite(fit).all()
+    return dict(value=NP * gens / el, unit="trial evals/s", cores=threads,
+                kind="oracle",
+                sample=(f"{gens} generation(s) of 1 run (NP={NP}, D={D}, "
+                        f"{w['kind']}) in FP64, {el:.1f} s, OpenMP over "
+                        f"individuals"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="rot1000_bf16",
+                    choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the DE step is single-GPU in "
+              "this build (independent runs would shard across GPUs with no "
+              "exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    main_res = time_workload(args.workload, args.steps, args.warmup)
+    w = WORKLOADS[args.workload]
+    line = {
+        "metric": "trial evals/sec and gens/sec at NP=1024,D=1000 "
+                  "(% roofline); wall-time to target",
+        "value": round(main_res["evals_per_s"], 1),
+        "unit": "trial evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if w["gemm_prec"] == "bf16" and w["kind"] == "rot_osc"
+                 else "f32",
+        "data": "synthetic",
+        "config": {"workload": describe(args.workload),
+                   "runs": w["runs"], "NP": w["NP"], "D": w["D"],
+                   "objective": w["kind"], "gemm": w["gemm_prec"]},
+        "gens_per_s": round(main_res["gens_per_s"], 2),
+        "kernel_ms_per_step": round(main_res["kernel_ms"], 5),
+        "roofline": main_res["roofline"],
+    }
+    if not args.no_extras:
+        comp = "sphere1000" if w["kind"] == "rot_osc" else "rot1000_bf16"
+        c = time_workload(comp, max(50, args.steps // 2), args.warmup)
+        line["companion"] = {
+            "workload": describe(comp), "evals_per_s": round(c["evals_per_s"], 1),
+            "gens_per_s": round(c["gens_per_s"], 2),
+            "kernel_ms_per_step": round(c["kernel_ms"], 5),
+            "roofline": c["roofline"]}
+        line["time_to_target"] = time_to_target()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,491 @@
+// de_api.hip -- host runtime behind the C ABI of include/de.h.
+//
+// Validation (synchronous, before any launch), workspace layout, the
+// generation counter and ping-pong parity, the host side of the
+// early-stopping loop, and error mapping.  All device work is launched
+// through de_internal.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <new>
+#include <unordered_set>
+
+#include "de.h"
+#include "de_internal.h"
+
+namespace {
+
+using de::GenArgs;
+
+constexpr uint64_t kMagic = 0x4445'6d69'3335'3578ull;
+constexpr int64_t kGenLimit = int64_t(1) << 32;  // counter field is 32-bit
+
+struct Layout {
+  size_t best, hit, acc, done, opad, rop, total;
+};
+
+size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+int dpad_for(int D) { return (int)round_up((size_t)D, 64); }
+
+Layout layout_for(const de_params& p, int kind, int prec) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round_up(bytes, 256);
+    return o;
+  };
+  const int dpad = dpad_for(p.D);
+  L.best = take(8 * (size_t)p.runs);
+  L.hit = take(8 * (size_t)p.runs);
+  L.acc = take(8 * (size_t)p.runs);
+  L.done = take(4);
+  L.opad = take(4 * (size_t)dpad);
+  L.rop = 0;
+  if (kind == de::kObjRotOsc)
+    L.rop = take((size_t)dpad * dpad * (prec == de::kPrecBF16 ? 2 : 4));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct de_state {
+  uint64_t magic;
+  de_params p;
+  int kind, prec, dpad, ldx;
+  float* pop[2];
+  float* fit[2];
+  char* work;
+  Layout L;
+  int64_t gen;
+  uint32_t cr_threshold;
+  float target;  // -inf outside de_evolve: no hit bookkeeping
+  hipStream_t last_stream;
+};
+
+namespace {
+
+std::mutex g_live_mu;
+std::unordered_set<const de_state*> g_live;
+
+bool live(const de_state* s) {
+  if (!s) return false;
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return g_live.count(s) != 0 && s->magic == kMagic;
+}
+
+bool aligned(const void* p, size_t a) {
+  return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+de_status check_problem(const de_params* p, const de_objective* o) {
+  if (!p || !o) return DE_E_INVAL;
+  if (p->runs < 1 || p->runs >= (1 << 24)) return DE_E_INVAL;
+  if (p->NP < 4 || p->D < 1) return DE_E_INVAL;
+  if ((int64_t)p->runs * p->NP > std::numeric_limits<int32_t>::max())
+    return DE_E_INVAL;
+  if (!std::isfinite(p->F) || !(p->F > 0.f)) return DE_E_INVAL;
+  if (!(p->CR >= 0.f && p->CR <= 1.f)) return DE_E_INVAL;
+  if (!std::isfinite(p->lo) || !std::isfinite(p->hi) || !(p->lo < p->hi) ||
+      !std::isfinite(p->hi - p->lo))
+    return DE_E_INVAL;
+  if (o->reserved != 0) return DE_E_INVAL;
+  if (o->kind != de::kObjSphere && o->kind != de::kObjRotOsc)
+    return DE_E_INVAL;
+  if (!o->o || !aligned(o->o, 4)) return DE_E_INVAL;
+  if (o->kind == de::kObjRotOsc) {
+    if (o->gemm_prec != de::kPrecF32 && o->gemm_prec != de::kPrecBF16)
+      return DE_E_INVAL;
+    if (!o->R || !aligned(o->R, 4) || o->ldr < p->D) return DE_E_INVAL;
+    const int dpad = dpad_for(p->D);
+    if (de::rot_lds_bytes_host(o->gemm_prec, dpad) > (size_t)de::kMaxLdsBytes)
+      return DE_E_UNSUPPORTED;
+  } else {
+    if (!de::sep_supported(p->D)) return DE_E_UNSUPPORTED;
+  }
+  return DE_OK;
+}
+
+de_status check_rows(const void* x, int32_t n_rows_hint, int32_t ldx, int D) {
+  (void)n_rows_hint;
+  if (!x || !aligned(x, 16)) return DE_E_INVAL;
+  if (ldx < D || ldx % 4 != 0) return DE_E_INVAL;
+  return DE_OK;
+}
+
+de_status from_hip(hipError_t e) { return e == hipSuccess ? DE_OK : DE_E_DEVICE; }
+
+GenArgs base_args(const de_state* s) {
+  GenArgs a{};
+  a.o = reinterpret_cast<const float*>(s->work + s->L.opad);
+  a.rop = s->L.rop ? s->work + s->L.rop : nullptr;
+  a.best_key = reinterpret_cast<unsigned long long*>(s->work + s->L.best);
+  a.hit_gen = reinterpret_cast<unsigned long long*>(s->work + s->L.hit);
+  a.accepted = reinterpret_cast<unsigned long long*>(s->work + s->L.acc);
+  a.done = reinterpret_cast<unsigned int*>(s->work + s->L.done);
+  a.runs = s->p.runs;
+  a.NP = s->p.NP;
+  a.D = s->p.D;
+  a.ldx = s->ldx;
+  a.dpad = s->dpad;
+  a.nrows = s->p.runs * s->p.NP;
+  a.F = s->p.F;
+  a.lo = s->p.lo;
+  a.hi = s->p.hi;
+  a.target = s->target;
+  a.cr_threshold = s->cr_threshold;
+  a.gen = (uint32_t)s->gen;
+  a.key_lo = (uint32_t)s->p.seed;
+  a.key_hi = (uint32_t)(s->p.seed >> 32);
+  return a;
+}
+
+// f of pop[gen & 1] into fit[gen & 1], then statistics restart.
+de_status eval_current_and_reset(de_state* s, hipStream_t st) {
+  GenArgs a = base_args(s);
+  const int b = (int)(s->gen & 1);
+  a.pop_cur = s->pop[b];
+  a.fit_next = s->fit[b];
+  de_status rc = from_hip(de::launch_eval(a, s->kind, s->prec, st));
+  if (rc != DE_OK) return rc;
+  rc = from_hip(de::launch_stats_reset(a, true, st));
+  if (rc != DE_OK) return rc;
+  a.fit_cur = s->fit[b];
+  return from_hip(de::launch_best_from_fit(a, st));
+}
+
+// Largest float <= t (so that f <= t in float equals f <= t exactly).
+float float_at_or_below(double t) {
+  if (std::isinf(t)) return (float)t;
+  if (t >= (double)std::numeric_limits<float>::max())
+    return std::numeric_limits<float>::max();
+  if (t <= -(double)std::numeric_limits<float>::max())
+    return -std::numeric_limits<float>::infinity();
+  float f = (float)t;
+  if ((double)f > t) f = std::nextafter(f, -std::numeric_limits<float>::infinity());
+  return f;
+}
+
+unsigned long long key_of(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return (unsigned long long)ord << 32;
+}
+
+float f_of_key(unsigned long long key) {
+  const uint32_t ord = (uint32_t)(key >> 32);
+  const uint32_t b = (ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+de_status run_generations(de_state* s, int64_t n, hipStream_t st) {
+  for (int64_t k = 0; k < n; ++k) {
+    GenArgs a = base_args(s);
+    const int b = (int)(s->gen & 1);
+    a.pop_cur = s->pop[b];
+    a.fit_cur = s->fit[b];
+    a.pop_next = s->pop[b ^ 1];
+    a.fit_next = s->fit[b ^ 1];
+    const de_status rc =
+        from_hip(de::launch_generation(a, s->kind, s->prec, st));
+    if (rc != DE_OK) return rc;
+    s->gen += 1;
+  }
+  return DE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+DE_API int32_t de_abi_version(void) { return DE_ABI_VERSION; }
+
+DE_API const char* de_strerror(de_status status) {
+  switch (status) {
+    case DE_OK: return "success";
+    case DE_E_INVAL: return "invalid argument";
+    case DE_E_NOMEM: return "host allocation failed";
+    case DE_E_DEVICE: return "HIP runtime or kernel failure";
+    case DE_E_STATE: return "invalid or destroyed handle, or wrong call order";
+    case DE_E_UNSUPPORTED: return "size not supported by this build";
+  }
+  return "unknown status";
+}
+
+DE_API de_status de_workspace_bytes(const de_params* params,
+                                    const de_objective* objective,
+                                    size_t* bytes) {
+  if (!bytes) return DE_E_INVAL;
+  const de_status rc = check_problem(params, objective);
+  if (rc != DE_OK) return rc;
+  *bytes = layout_for(*params, objective->kind, objective->gemm_prec).total;
+  return DE_OK;
+}
+
+DE_API de_status de_init_population(const de_params* params,
+                                    const de_objective* objective,
+                                    const de_buffers* buffers,
+                                    void* hip_stream, de_state** out) {
+  if (!out || !buffers) return DE_E_INVAL;
+  de_status rc = check_problem(params, objective);
+  if (rc != DE_OK) return rc;
+  const de_params& p = *params;
+  const int prec = objective->kind == de::kObjRotOsc ? objective->gemm_prec
+                                                     : de::kPrecF32;
+  if (buffers->reserved != 0) return DE_E_INVAL;
+  for (int b = 0; b < 2; ++b) {
+    if (check_rows(buffers->pop[b], 0, buffers->ldx, p.D) != DE_OK)
+      return DE_E_INVAL;
+    if (!buffers->fit[b] || !aligned(buffers->fit[b], 4)) return DE_E_INVAL;
+  }
+  if (buffers->pop[0] == buffers->pop[1] || buffers->fit[0] == buffers->fit[1])
+    return DE_E_INVAL;
+  if ((uint64_t)p.runs * p.NP * (uint64_t)buffers->ldx >
+      (uint64_t)std::numeric_limits<int64_t>::max() / 4)
+    return DE_E_INVAL;
+  const Layout L = layout_for(p, objective->kind, prec);
+  if (!buffers->work || !aligned(buffers->work, 256) ||
+      buffers->work_bytes < L.total)
+    return DE_E_INVAL;
+
+  (void)hipGetLastError();  // clear a stale error left by unrelated calls
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (objective->kind == de::kObjRotOsc) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DE_E_DEVICE;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              dev) != hipSuccess)
+      return DE_E_DEVICE;
+    if (de::rot_lds_bytes_host(prec, dpad_for(p.D)) > (size_t)lds)
+      return DE_E_UNSUPPORTED;
+  }
+
+  de_state* s = new (std::nothrow) de_state();
+  if (!s) return DE_E_NOMEM;
+  s->magic = kMagic;
+  s->p = p;
+  s->kind = objective->kind;
+  s->prec = prec;
+  s->dpad = dpad_for(p.D);
+  s->ldx = buffers->ldx;
+  for (int b = 0; b < 2; ++b) {
+    s->pop[b] = buffers->pop[b];
+    s->fit[b] = buffers->fit[b];
+  }
+  s->work = reinterpret_cast<char*>(buffers->work);
+  s->L = L;
+  s->gen = 0;
+  s->cr_threshold = (uint32_t)std::floor((double)p.CR * 16777216.0);
+  s->target = -std::numeric_limits<float>::infinity();
+  s->last_stream = st;
+
+  rc = from_hip(de::launch_prep(objective->o, objective->R, objective->ldr,
+                                p.D, s->dpad, s->kind, s->prec,
+                                reinterpret_cast<float*>(s->work + L.opad),
+                                L.rop ? s->work + L.rop : nullptr, st));
+  if (rc == DE_OK) {
+    GenArgs a = base_args(s);
+    a.pop_next = s->pop[0];
+    rc = from_hip(de::launch_init(a, st));
+  }
+  if (rc == DE_OK) rc = eval_current_and_reset(s, st);
+  if (rc != DE_OK) {
+    s->magic = 0;
+    delete s;
+    return rc;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(s);
+  }
+  *out = s;
+  return DE_OK;
+}
+
+DE_API de_status de_generation(de_state* state, int32_t n_gens,
+                               void* hip_stream) {
+  if (!live(state)) return DE_E_STATE;
+  if (n_gens < 0) return DE_E_INVAL;
+  if (state->gen + n_gens >= kGenLimit) return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  state->last_stream = st;
+  return run_generations(state, n_gens, st);
+}
+
+DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
+                           int32_t check_every, void* hip_stream,
+                           int64_t* gens_done, int64_t* hit_gen) {
+  if (!live(state)) return DE_E_STATE;
+  if (max_gens < 0 || check_every < 1 || std::isnan(target) || !gens_done)
+    return DE_E_INVAL;
+  if (state->gen + max_gens >= kGenLimit) return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  state->last_stream = st;
+  *gens_done = 0;
+  const float t32 = float_at_or_below(target);
+  GenArgs a = base_args(state);
+  de_status rc = DE_OK;
+  // hit bookkeeping restarts for this target: clear, then runs already at
+  // or below it hit at the current generation
+  {
+    GenArgs r = a;
+    rc = from_hip(de::launch_stats_reset(r, false, st));
+    // launch_stats_reset also clears best; rebuild it from the current fit
+    if (rc == DE_OK) {
+      r.fit_cur = state->fit[state->gen & 1];
+      rc = from_hip(de::launch_best_from_fit(r, st));
+    }
+    if (rc == DE_OK) rc = from_hip(de::launch_hit_check(r, key_of(t32), st));
+  }
+  state->target = t32;
+  int64_t done_gens = 0;
+  while (rc == DE_OK) {
+    unsigned int done = 0;
+    rc = from_hip(hipMemcpyAsync(&done, a.done, sizeof(done),
+                                 hipMemcpyDeviceToHost, st));
+    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc != DE_OK) break;
+    if ((int)done >= state->p.runs || done_gens >= max_gens) break;
+    const int64_t n = std::min<int64_t>(check_every, max_gens - done_gens);
+    rc = run_generations(state, n, st);
+    done_gens += n;
+  }
+  state->target = -std::numeric_limits<float>::infinity();
+  *gens_done = done_gens;
+  if (rc == DE_OK && hit_gen) {
+    const int runs = state->p.runs;
+    unsigned long long* tmp = new (std::nothrow) unsigned long long[runs];
+    if (!tmp) return DE_E_NOMEM;
+    rc = from_hip(hipMemcpyAsync(tmp, a.hit_gen, 8 * (size_t)runs,
+                                 hipMemcpyDeviceToHost, st));
+    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK)
+      for (int r = 0; r < runs; ++r)
+        hit_gen[r] = tmp[r] == ~0ull ? -1 : (int64_t)tmp[r];
+    delete[] tmp;
+  }
+  return rc;
+}
+
+DE_API de_status de_best(de_state* state, int32_t run, void* hip_stream,
+                         float* x_host, double* f_host, int32_t* idx_host) {
+  if (!live(state)) return DE_E_STATE;
+  if (run < 0 || run >= state->p.runs || !f_host) return DE_E_INVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const GenArgs a = base_args(state);
+  unsigned long long key = 0;
+  de_status rc = from_hip(hipMemcpyAsync(&key, a.best_key + run, 8,
+                                         hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc != DE_OK) return rc;
+  if (key == ~0ull) return DE_E_STATE;
+  const int32_t idx = (int32_t)(key & 0xFFFFFFFFu);
+  if (idx < 0 || idx >= state->p.NP) return DE_E_STATE;
+  *f_host = (double)f_of_key(key);
+  if (idx_host) *idx_host = idx;
+  if (x_host) {
+    const float* row = state->pop[state->gen & 1] +
+                       ((size_t)run * state->p.NP + idx) * state->ldx;
+    rc = from_hip(hipMemcpyAsync(x_host, row, sizeof(float) * state->p.D,
+                                 hipMemcpyDeviceToHost, st));
+    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  }
+  return rc;
+}
+
+DE_API de_status de_get_generation(const de_state* state, int64_t* gen) {
+  if (!live(state)) return DE_E_STATE;
+  if (!gen) return DE_E_INVAL;
+  *gen = state->gen;
+  return DE_OK;
+}
+
+DE_API de_status de_read_stats(de_state* state, void* hip_stream,
+                               int64_t* accepted, double* best_f) {
+  if (!live(state)) return DE_E_STATE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const GenArgs a = base_args(state);
+  const int runs = state->p.runs;
+  unsigned long long* tmp = new (std::nothrow) unsigned long long[2 * runs];
+  if (!tmp) return DE_E_NOMEM;
+  de_status rc = from_hip(hipMemcpyAsync(tmp, a.accepted, 8 * (size_t)runs,
+                                         hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK)
+    rc = from_hip(hipMemcpyAsync(tmp + runs, a.best_key, 8 * (size_t)runs,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) {
+    for (int r = 0; r < runs; ++r) {
+      if (accepted) accepted[r] = (int64_t)tmp[r];
+      if (best_f) best_f[r] = (double)f_of_key(tmp[runs + r]);
+    }
+  }
+  delete[] tmp;
+  return rc;
+}
+
+DE_API de_status de_load_population(de_state* state, int64_t gen,
+                                    void* hip_stream) {
+  if (!live(state)) return DE_E_STATE;
+  if (gen < 0 || gen >= kGenLimit) return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  state->last_stream = st;
+  state->gen = gen;
+  return eval_current_and_reset(state, st);
+}
+
+DE_API de_status de_eval(de_state* state, const float* x_dev, int32_t n,
+                         int32_t ldx, float* f_dev, void* hip_stream) {
+  if (!live(state)) return DE_E_STATE;
+  if (n < 0) return DE_E_INVAL;
+  if (n == 0) return DE_OK;
+  if (check_rows(x_dev, n, ldx, state->p.D) != DE_OK) return DE_E_INVAL;
+  if (!f_dev || !aligned(f_dev, 4)) return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  GenArgs a = base_args(state);
+  a.pop_cur = x_dev;
+  a.fit_next = f_dev;
+  a.nrows = n;
+  a.ldx = ldx;
+  return from_hip(de::launch_eval(a, state->kind, state->prec, st));
+}
+
+DE_API de_status de_debug_draws(const de_state* state, int64_t gen,
+                                int32_t* idx4_dev, uint32_t* mask_dev,
+                                void* hip_stream) {
+  if (!live(state)) return DE_E_STATE;
+  if (gen < 0 || gen >= kGenLimit) return DE_E_INVAL;
+  if (!idx4_dev && !mask_dev) return DE_OK;
+  (void)hipGetLastError();
+  GenArgs a = base_args(state);
+  a.gen = (uint32_t)gen;
+  return from_hip(de::launch_debug_draws(
+      a, idx4_dev, mask_dev, reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+DE_API de_status de_destroy(de_state* state) {
+  if (!state) return DE_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (!g_live.count(state)) return DE_E_STATE;
+    g_live.erase(state);
+  }
+  state->magic = 0;
+  delete state;
+  return DE_OK;
+}
+
+}  // extern "C"

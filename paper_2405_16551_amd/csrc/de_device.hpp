@@ -1,0 +1,154 @@
+// de_device.hpp -- device-side building blocks of the gfx950 DE/rand/1/bin
+// kernels: counter-based random draws, the donor sampler of eq. 2, the
+// crossover test of eq. 3, bound repair, ordered (f, index) keys and
+// wave64 reductions.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  The
+// 128-bit counter is (q, i, gen, tag << 24 | run) and the key is the 64-bit
+// seed, so every draw is a pure function of its coordinates and no
+// generator state lives in memory.  Integer-only conversions keep every
+// index and every crossover decision independent of floating point.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace de {
+
+enum : uint32_t { kTagInit = 1u, kTagIdx = 2u, kTagXover = 3u };
+
+// Philox4x32-10 multipliers and Weyl key increments (Salmon et al., Sec. 4).
+constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
+constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
+constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
+
+struct Words4 {
+  uint32_t w[4];
+};
+
+// One S-box round: two 32x32->64 products (v_mad_u64_u32 on CDNA), the
+// high halves mixed with the other two counter words and the round key.
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
+                                             uint32_t& c2, uint32_t& c3,
+                                             uint32_t k0, uint32_t k1) {
+  const uint64_t pa = (uint64_t)kPhiloxMulA * c0;
+  const uint64_t pb = (uint64_t)kPhiloxMulB * c2;
+  const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+  const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+  c1 = (uint32_t)pb;
+  c3 = (uint32_t)pa;
+  c0 = n0;
+  c2 = n2;
+}
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
+                                                uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c0, c1, c2, c3, k0 + (uint32_t)r * kPhiloxWeylA,
+                 k1 + (uint32_t)r * kPhiloxWeylB);
+  }
+  Words4 out;
+  out.w[0] = c0;
+  out.w[1] = c1;
+  out.w[2] = c2;
+  out.w[3] = c3;
+  return out;
+}
+
+// Draw block for (tag, run, gen, individual, group q).
+__device__ __forceinline__ Words4 draw_block(uint32_t tag, uint32_t run,
+                                             uint32_t gen, uint32_t indiv,
+                                             uint32_t q, uint32_t key_lo,
+                                             uint32_t key_hi) {
+  return philox4x32_10(q, indiv, gen, (tag << 24) | run, key_lo, key_hi);
+}
+
+// Uniform integer in [0, n) from one 32-bit word: floor(w * n / 2^32).
+__device__ __forceinline__ int uniform_below(uint32_t w, uint32_t n) {
+  return (int)__umulhi(w, n);
+}
+
+// Donor triple and j_rand of eq. 2 / eq. 3 for target i.  a, b, c are
+// uniform over NP-1, NP-2, NP-3 values; each is lifted over the indices
+// already taken (target first, then earlier donors), in ascending order, so
+// (a, b, c) maps one-to-one onto ordered triples of distinct indices != i.
+struct Donors {
+  int r1, r2, r3, jrand;
+};
+
+__device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t gen,
+                                              int i, int NP, int D,
+                                              uint32_t key_lo,
+                                              uint32_t key_hi) {
+  const Words4 w = draw_block(kTagIdx, run, gen, (uint32_t)i, 0u, key_lo,
+                              key_hi);
+  Donors d;
+  const int a = uniform_below(w.w[0], (uint32_t)(NP - 1));
+  d.r1 = a + (a >= i ? 1 : 0);
+  const int lo2 = min(i, d.r1), hi2 = max(i, d.r1);
+  int b = uniform_below(w.w[1], (uint32_t)(NP - 2));
+  b += (b >= lo2 ? 1 : 0);
+  b += (b >= hi2 ? 1 : 0);
+  d.r2 = b;
+  // ascending order of {i, r1, r2}
+  int s0 = lo2, s1 = hi2, s2 = b;
+  if (s2 < s1) { const int t = s1; s1 = s2; s2 = t; }
+  if (s1 < s0) { const int t = s0; s0 = s1; s1 = t; }
+  int c = uniform_below(w.w[2], (uint32_t)(NP - 3));
+  c += (c >= s0 ? 1 : 0);
+  c += (c >= s1 ? 1 : 0);
+  c += (c >= s2 ? 1 : 0);
+  d.r3 = c;
+  d.jrand = uniform_below(w.w[3], (uint32_t)D);
+  return d;
+}
+
+// Crossover test of eq. 3 for coordinate j = 4q + b: rand_j = (w >> 8) 2^-24
+// and rand_j <= CR  <=>  (w >> 8) <= floor(CR 2^24) = cr_threshold.
+__device__ __forceinline__ bool take_mutant(uint32_t word, int j, int jrand,
+                                            uint32_t cr_threshold) {
+  return (j == jrand) || ((word >> 8) <= cr_threshold);
+}
+
+// Mutant coordinate of eq. 2 with clamping to the box; NaN passes through.
+__device__ __forceinline__ float mutant_coord(float x1, float x2, float x3,
+                                              float F, float lo, float hi) {
+  float v = fmaf(F, x2 - x3, x1);
+  v = v < lo ? lo : v;
+  v = v > hi ? hi : v;
+  return v;
+}
+
+// Totally ordered 64-bit key: order-preserving image of the float in the high
+// half (NaN sorts above +inf), individual index in the low half, so
+// atomicMin yields the lowest value with ties to the lowest index.
+__device__ __forceinline__ unsigned long long fit_key(float f, int idx) {
+  const uint32_t b = __float_as_uint(f);
+  const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((unsigned long long)ord << 32) | (uint32_t)idx;
+}
+
+// Sum over aligned groups of `width` lanes (power of two <= 64) by
+// butterfly exchange; every lane of the group ends with the same total, and
+// the order of additions is fixed.
+template <int width>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int m = width / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Block index remapping so that consecutive logical blocks land on the same
+// XCD (gfx950 dispatches block b to XCD b mod 8): logical block ranges, and
+// the donor rows they share, then stay in one XCD's L2.  Bijective for any n.
+__device__ __forceinline__ int xcd_logical_block(int b, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd;
+  const int xcd = b % kXcd, k = b / kXcd;
+  return xcd * q + min(xcd, r) + k;
+}
+
+}  // namespace de

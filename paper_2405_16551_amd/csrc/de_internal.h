@@ -1,0 +1,50 @@
+// de_internal.h -- launch interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace de {
+
+enum { kObjSphere = 0, kObjRotOsc = 1 };
+enum { kPrecF32 = 0, kPrecBF16 = 1 };
+
+constexpr int kMaxLdsBytes = 160 * 1024;  // gfx950 LDS per workgroup
+
+// Everything one generation launch needs, passed by value.
+struct GenArgs {
+  const float* pop_cur;   // generation g rows (EVAL: rows to evaluate)
+  float* pop_next;        // generation g+1 rows (init: generation 0)
+  const float* fit_cur;   // f of generation g
+  float* fit_next;        // f of generation g+1 (EVAL: output values)
+  const float* o;         // shift, zero-padded to dpad
+  const void* rop;        // R in the MFMA B-operand layout (rotated only)
+  unsigned long long* best_key;  // [runs] ordered (f, index) keys
+  unsigned long long* hit_gen;   // [runs] first generation with best <= target
+  unsigned long long* accepted;  // [runs] accepted trials
+  unsigned int* done;            // runs that have hit the target
+  int runs, NP, D, ldx, dpad, nrows;
+  float F, lo, hi, target;
+  uint32_t cr_threshold, gen, key_lo, key_hi;
+};
+
+size_t rot_lds_bytes_host(int prec, int dpad);
+bool sep_supported(int D);
+
+hipError_t launch_generation(const GenArgs& a, int kind, int prec,
+                             hipStream_t s);
+hipError_t launch_eval(const GenArgs& a, int kind, int prec, hipStream_t s);
+hipError_t launch_init(const GenArgs& a, hipStream_t s);
+hipError_t launch_prep(const float* o, const float* R, int ldr, int D,
+                       int dpad, int kind, int prec, float* o_pad, void* rop,
+                       hipStream_t s);
+hipError_t launch_stats_reset(const GenArgs& a, bool reset_accepted,
+                              hipStream_t s);
+hipError_t launch_best_from_fit(const GenArgs& a, hipStream_t s);
+hipError_t launch_hit_check(const GenArgs& a, unsigned long long target_key,
+                            hipStream_t s);
+hipError_t launch_debug_draws(const GenArgs& a, int* idx4, uint32_t* mask,
+                              hipStream_t s);
+
+}  // namespace de

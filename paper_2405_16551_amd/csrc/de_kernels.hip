@@ -1,0 +1,688 @@
+// de_kernels.hip -- gfx950 kernels of the DE/rand/1/bin generation step.
+//
+// One launch advances every run by one synchronous generation (Section 2 of
+// arXiv 2405.16551): draws, DE/rand/1 mutation (eq. 2) with clamping,
+// binomial crossover (eq. 3), fitness of the trial vector, greedy selection,
+// write of generation g+1 into the other ping-pong buffer and the per-run
+// statistics.  Two fused kernels cover the two objective families of
+// Section 7.3.1:
+//
+//   k_sep   separable objective (shifted sphere).  A group of LPI lanes owns
+//           one individual; each lane owns 4 consecutive coordinates per
+//           step (one Philox block, one float4 of each row).  HBM-bound.
+//   k_rot   rotated objective z = R (x - o), f = sum z^2 + sin^2(3z).  A
+//           workgroup owns a tile of BM trial rows: it builds them into LDS
+//           as the A operand, runs Z = Y R^T on MFMA with the objective and
+//           row sum fused into the epilogue, then selects and writes.  R is
+//           read from L2 in a fragment-major layout prepared once.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "de_device.hpp"
+#include "de_internal.h"
+
+namespace de {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr unsigned long long kNoHit = ~0ull;
+
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) {
+  *reinterpret_cast<float4*>(p) = v;
+}
+__device__ __forceinline__ float get(const float4& v, int b) {
+  return b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ void set(float4& v, int b, float s) {
+  if (b == 0) v.x = s; else if (b == 1) v.y = s; else if (b == 2) v.z = s;
+  else v.w = s;
+}
+
+// Statistics after an accepted trial with value f of individual i in run r,
+// which produced generation gen+1.
+__device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
+                                              float f) {
+  atomicAdd(&a.accepted[run], 1ull);
+  atomicMin(&a.best_key[run], fit_key(f, i));
+  if (f <= a.target) {
+    const unsigned long long old =
+        atomicMin(&a.hit_gen[run], (unsigned long long)a.gen + 1ull);
+    if (old == kNoHit) atomicAdd(a.done, 1u);
+  }
+}
+
+// Trial coordinates j0..j0+3 of one individual (eqs. 2, 3); coordinates at
+// or beyond D keep the target's value.
+__device__ __forceinline__ float4 trial4(const GenArgs& a, uint32_t run,
+                                         int i, int q, const Donors& d,
+                                         const float* x1, const float* x2,
+                                         const float* x3, float4 xv,
+                                         uint32_t* take_bits) {
+  const int j0 = 4 * q;
+  const Words4 w = draw_block(kTagXover, run, a.gen, (uint32_t)i, (uint32_t)q,
+                              a.key_lo, a.key_hi);
+  const float4 v1 = ld4(x1 + j0), v2 = ld4(x2 + j0), v3 = ld4(x3 + j0);
+  float4 u = xv;
+  uint32_t bits = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const bool t = (j0 + b < a.D) && take_mutant(w.w[b], j0 + b, d.jrand,
+                                                 a.cr_threshold);
+    if (t) {
+      set(u, b, mutant_coord(get(v1, b), get(v2, b), get(v3, b), a.F, a.lo,
+                             a.hi));
+      bits |= 1u << b;
+    }
+  }
+  if (take_bits) *take_bits = bits;
+  return u;
+}
+
+// ---------------------------------------------------------------------------
+// Separable objective.  EVAL: f of rows pop_cur[0..nrows) into fit_next.
+template <int LPI, int ITER, bool EVAL>
+__global__ __launch_bounds__(256) void k_sep(GenArgs a) {
+  constexpr int IPB = 256 / LPI;
+  const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+  const int slot = (int)threadIdx.x / LPI, ln = (int)threadIdx.x % LPI;
+  const int g = lb * IPB + slot;
+  if (g >= a.nrows) return;  // whole LPI-groups leave together
+  const int run = EVAL ? 0 : g / a.NP;
+  const int i = EVAL ? g : g - run * a.NP;
+  const float* xrow = a.pop_cur + (size_t)g * a.ldx;
+
+  Donors d{0, 0, 0, 0};
+  const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
+  if (!EVAL) {
+    d = pick_donors((uint32_t)run, a.gen, i, a.NP, a.D, a.key_lo, a.key_hi);
+    const float* base = a.pop_cur + (size_t)run * a.NP * a.ldx;
+    x1 = base + (size_t)d.r1 * a.ldx;
+    x2 = base + (size_t)d.r2 * a.ldx;
+    x3 = base + (size_t)d.r3 * a.ldx;
+  }
+  float4 xv[ITER], uv[ITER];
+  float acc = 0.f;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int q = ln + it * LPI, j0 = 4 * q;
+    if (j0 < a.D) {
+      xv[it] = ld4(xrow + j0);
+      uv[it] = EVAL ? xv[it]
+                    : trial4(a, (uint32_t)run, i, q, d, x1, x2, x3, xv[it],
+                             nullptr);
+      const float4 ov = ld4(a.o + j0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (j0 + b < a.D) {
+          const float y = get(uv[it], b) - get(ov, b);
+          acc = fmaf(y, y, acc);
+        }
+      }
+    }
+  }
+  const float f = group_sum<LPI>(acc);
+  if (EVAL) {
+    if (ln == 0) a.fit_next[g] = f;
+    return;
+  }
+  const float fx = a.fit_cur[g];
+  const bool accept = f < fx;
+  float* nrow = a.pop_next + (size_t)g * a.ldx;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int j0 = 4 * (ln + it * LPI);
+    if (j0 < a.D) st4(nrow + j0, accept ? uv[it] : xv[it]);
+  }
+  if (ln == 0) {
+    a.fit_next[g] = accept ? f : fx;
+    if (accept) record_accept(a, run, i, f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rotated objective.  Tile of BM rows per 512-thread workgroup.
+//   phase 1: trial rows -> LDS A tile (y = u - o in the GEMM precision) and
+//            crossover bit planes; padding rows/columns are zero.
+//   phase 2: Z = Y R^T, 32x32 MFMA blocks, wave tile BM x 64 columns,
+//            epilogue z^2 + sin^2(3z) summed per row in registers.
+//   phase 3: row totals -> selection -> next generation rows, statistics.
+struct PrecBF16 {
+  using T = __bf16;
+  static constexpr int BM = 64;
+  static constexpr int MB = 2;  // 32-row MFMA blocks per tile
+  __host__ __device__ static constexpr int stride(int dpad) { return dpad + 8; }
+};
+struct PrecF32 {
+  using T = float;
+  static constexpr int BM = 32;
+  static constexpr int MB = 1;
+  __host__ __device__ static constexpr int stride(int dpad) { return dpad + 4; }
+};
+
+constexpr int kRotThreads = 512;
+constexpr int kRotWaves = kRotThreads / 64;
+constexpr int kNB = 2;  // 32-column MFMA blocks per wave per chunk
+
+template <class P>
+__host__ __device__ constexpr size_t rot_lds_bytes(int dpad) {
+  const int tq = (dpad / 4 + 63) / 64;
+  return (size_t)P::BM * P::stride(dpad) * sizeof(typename P::T)  // A tile
+         + (size_t)P::BM * tq * 4 * sizeof(unsigned long long)   // planes
+         + (size_t)P::BM * 4 * sizeof(int)                       // donors
+         + (size_t)kRotWaves * P::BM * sizeof(float);            // partials
+}
+
+// Position of coordinate k inside an LDS row.  BF16: natural order.  FP32:
+// within each group of 8, k = 2s + h is stored at 4h + s so that one lane's
+// four K-steps of the 32x32x2 MFMA are one 16-byte read.
+template <class P>
+__device__ __forceinline__ int lds_col(int k) {
+  if constexpr (sizeof(typename P::T) == 2) {
+    return k;
+  } else {
+    const int g = k & ~7, r = k & 7;
+    return g + (r & 1) * 4 + (r >> 1);
+  }
+}
+
+__device__ __forceinline__ float osc_term(float z) {
+  const float s = sinf(3.0f * z);
+  return fmaf(z, z, s * s);
+}
+
+template <class P, bool EVAL>
+__global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
+  using T = typename P::T;
+  constexpr int BM = P::BM, MB = P::MB;
+  extern __shared__ __align__(16) char smem[];
+  const int dpad = a.dpad;
+  const int stride = P::stride(dpad);
+  const int tq = (dpad / 4 + 63) / 64;
+  T* At = reinterpret_cast<T*>(smem);
+  unsigned long long* planes = reinterpret_cast<unsigned long long*>(
+      smem + (size_t)BM * stride * sizeof(T));
+  int* donors = reinterpret_cast<int*>(planes + (size_t)BM * tq * 4);
+  float* fpart = reinterpret_cast<float*>(donors + BM * 4);
+
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+  int run = 0, row0 = 0, nvalid = 0;
+  if (EVAL) {
+    row0 = lb * BM;
+    nvalid = min(BM, a.nrows - row0);
+  } else {
+    const int tiles = (a.NP + BM - 1) / BM;
+    run = lb / tiles;
+    row0 = (lb - run * tiles) * BM;
+    nvalid = min(BM, a.NP - row0);
+  }
+  const float* base = a.pop_cur + (EVAL ? 0 : (size_t)run * a.NP * a.ldx);
+
+  // ---- phase 1: build the A tile
+  for (int rl = wave; rl < BM; rl += kRotWaves) {
+    T* arow = At + (size_t)rl * stride;
+    if (rl >= nvalid) {
+      for (int k = lane; k < dpad; k += 64) arow[k] = (T)0.0f;
+      continue;
+    }
+    const int i = row0 + rl;
+    const float* xrow = base + (size_t)i * a.ldx;
+    Donors d{0, 0, 0, 0};
+    const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
+    if (!EVAL) {
+      d = pick_donors((uint32_t)run, a.gen, i, a.NP, a.D, a.key_lo, a.key_hi);
+      x1 = base + (size_t)d.r1 * a.ldx;
+      x2 = base + (size_t)d.r2 * a.ldx;
+      x3 = base + (size_t)d.r3 * a.ldx;
+      if (lane == 0) {
+        donors[rl * 4 + 0] = d.r1;
+        donors[rl * 4 + 1] = d.r2;
+        donors[rl * 4 + 2] = d.r3;
+        donors[rl * 4 + 3] = d.jrand;
+      }
+    }
+    for (int t = 0; t < tq; ++t) {
+      const int q = lane + 64 * t, j0 = 4 * q;
+      uint32_t bits = 0;
+      float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j0 < a.D) {
+        const float4 xv = ld4(xrow + j0);
+        const float4 u = EVAL ? xv
+                              : trial4(a, (uint32_t)run, i, q, d, x1, x2, x3,
+                                       xv, &bits);
+        const float4 ov = ld4(a.o + j0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          set(y, b, (j0 + b < a.D) ? get(u, b) - get(ov, b) : 0.f);
+      }
+      if (j0 < dpad) {
+        if constexpr (sizeof(T) == 2) {
+          bf16x4 yb;
+          yb[0] = (__bf16)y.x;
+          yb[1] = (__bf16)y.y;
+          yb[2] = (__bf16)y.z;
+          yb[3] = (__bf16)y.w;
+          *reinterpret_cast<bf16x4*>(arow + j0) = yb;
+        } else {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) arow[lds_col<P>(j0 + b)] = get(y, b);
+        }
+      }
+      if (!EVAL) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const unsigned long long m = __ballot((bits >> b) & 1u);
+          if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: Z = Y R^T with the objective fused into the epilogue
+  const int nblk = dpad / 32;
+  float part[MB][16];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) part[mb][r] = 0.f;
+
+  for (int nb0 = wave * kNB; nb0 < nblk; nb0 += kRotWaves * kNB) {
+    floatx16 acc[MB][kNB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int t = 0; t < kNB; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[mb][t][r] = 0.f;
+
+    if constexpr (sizeof(T) == 2) {
+      // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per block
+      const bf16x8* rop = reinterpret_cast<const bf16x8*>(a.rop);
+      const int kbn = dpad / 16;
+      const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
+      const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
+      const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
+#pragma unroll 4
+      for (int kb = 0; kb < kbn; ++kb) {
+        const bf16x8 b0 = rb0[(size_t)kb * 64];
+        const bf16x8 b1 = rb1[(size_t)kb * 64];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(
+              ar + (size_t)mb * 32 * stride + kb * 16);
+          acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0,
+                                                               acc[mb][0], 0,
+                                                               0, 0);
+          acc[mb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1,
+                                                               acc[mb][1], 0,
+                                                               0, 0);
+        }
+      }
+    } else {
+      // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps
+      const float4* rop = reinterpret_cast<const float4*>(a.rop);
+      const int k8n = dpad / 8;
+      const float4* rb0 = rop + ((size_t)nb0 * k8n) * 64 + lane;
+      const float4* rb1 = rb0 + (size_t)k8n * 64;
+      const float* ar = reinterpret_cast<const float*>(At) +
+                        (size_t)(lane % 32) * stride + 4 * (lane / 32);
+#pragma unroll 2
+      for (int k8 = 0; k8 < k8n; ++k8) {
+        const float4 b0 = rb0[(size_t)k8 * 64];
+        const float4 b1 = rb1[(size_t)k8 * 64];
+        const float4 av = *reinterpret_cast<const float4*>(ar + k8 * 8);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+              get(av, s), get(b0, s), acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+              get(av, s), get(b1, s), acc[0][1], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int t = 0; t < kNB; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[mb][r] += osc_term(acc[mb][t][r]);
+  }
+  // 32x32 accumulator layout: register r of lane l holds row
+  // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float s = group_sum<32>(part[mb][r]);
+      if ((lane % 32) == 0) {
+        const int row = mb * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        fpart[wave * BM + row] = s;
+      }
+    }
+  __syncthreads();
+
+  // ---- phase 3: selection and the next generation
+  for (int rl = wave; rl < nvalid; rl += kRotWaves) {
+    float f = 0.f;
+#pragma unroll
+    for (int w = 0; w < kRotWaves; ++w) f += fpart[w * BM + rl];
+    const int i = row0 + rl;
+    if (EVAL) {
+      if (lane == 0) a.fit_next[i] = f;
+      continue;
+    }
+    const size_t g = (size_t)run * a.NP + i;
+    const float fx = a.fit_cur[g];
+    const bool accept = f < fx;
+    const float* xrow = base + (size_t)i * a.ldx;
+    float* nrow = a.pop_next + g * a.ldx;
+    const float* x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
+    const float* x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
+    const float* x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+    for (int t = 0; t < tq; ++t) {
+      const int q = lane + 64 * t, j0 = 4 * q;
+      if (j0 >= a.D) continue;
+      float4 xv = ld4(xrow + j0);
+      if (accept) {
+        const float4 v1 = ld4(x1 + j0), v2 = ld4(x2 + j0), v3 = ld4(x3 + j0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const unsigned long long m = planes[((size_t)rl * tq + t) * 4 + b];
+          if ((m >> lane) & 1ull)
+            set(xv, b, mutant_coord(get(v1, b), get(v2, b), get(v3, b), a.F,
+                                    a.lo, a.hi));
+        }
+      }
+      st4(nrow + j0, xv);
+    }
+    if (lane == 0) {
+      a.fit_next[g] = accept ? f : fx;
+      if (accept) record_accept(a, run, i, f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial population (Section 2): x = lo + u (hi - lo), u = k 2^-24.
+__global__ __launch_bounds__(256) void k_init(GenArgs a) {
+  const int nq = (a.D + 3) / 4;
+  const size_t total = (size_t)a.nrows * nq;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int g = (int)(t / nq), q = (int)(t % nq);
+    const int run = g / a.NP, i = g - run * a.NP;
+    const Words4 w = draw_block(kTagInit, (uint32_t)run, 0u, (uint32_t)i,
+                                (uint32_t)q, a.key_lo, a.key_hi);
+    const float span = a.hi - a.lo;
+    float4 v;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float u = (float)(w.w[b] >> 8) * 0x1.0p-24f;
+      set(v, b, fmaf(u, span, a.lo));
+    }
+    float* p = a.pop_next + (size_t)g * a.ldx + 4 * q;
+    if (4 * q + 4 <= a.D) {
+      st4(p, v);
+    } else {
+      for (int b = 0; 4 * q + b < a.D; ++b) p[b] = get(v, b);
+    }
+  }
+}
+
+// o -> zero-padded copy; R -> MFMA B-operand layout (zero-padded).
+__global__ __launch_bounds__(256) void k_prep_shift(const float* o, int D,
+                                                    int dpad, float* o_pad) {
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < dpad; k += gridDim.x * 256)
+    o_pad[k] = k < D ? o[k] : 0.f;
+}
+
+// BF16 layout: element (n, k) of R (z_n = sum_k R[n][k] y_k) goes to block
+// nb = n / 32, k-step kb = k / 16, lane (n % 32) + 32 ((k % 16) / 8),
+// slot k % 8.
+__global__ __launch_bounds__(256) void k_prep_rot_bf16(const float* R, int ldr,
+                                                       int D, int dpad,
+                                                       __bf16* rop) {
+  const size_t total = (size_t)dpad * dpad;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int n = (int)(t / dpad), k = (int)(t % dpad);
+    const float v = (n < D && k < D) ? R[(size_t)n * ldr + k] : 0.f;
+    const size_t nb = n / 32, kb = k / 16;
+    const int ln = (n % 32) + 32 * ((k % 16) / 8);
+    rop[((nb * (dpad / 16) + kb) * 64 + ln) * 8 + (k % 8)] = (__bf16)v;
+  }
+}
+
+// FP32 layout: block nb = n / 32, group k8 = k / 8, lane (n % 32) + 32 (k % 2),
+// slot (k % 8) / 2.
+__global__ __launch_bounds__(256) void k_prep_rot_f32(const float* R, int ldr,
+                                                      int D, int dpad,
+                                                      float* rop) {
+  const size_t total = (size_t)dpad * dpad;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int n = (int)(t / dpad), k = (int)(t % dpad);
+    const float v = (n < D && k < D) ? R[(size_t)n * ldr + k] : 0.f;
+    const size_t nb = n / 32, k8 = k / 8;
+    const int ln = (n % 32) + 32 * (k % 2);
+    rop[((nb * (dpad / 8) + k8) * 64 + ln) * 4 + (k % 8) / 2] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Statistics.
+__global__ void k_stats_reset(GenArgs a, int reset_accepted) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < a.runs;
+       r += gridDim.x * blockDim.x) {
+    a.best_key[r] = ~0ull;
+    a.hit_gen[r] = kNoHit;
+    if (reset_accepted) a.accepted[r] = 0ull;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.done = 0u;
+}
+
+// best_key[r] = min over i of key(fit[r][i], i); one wave per run slice.
+__global__ __launch_bounds__(256) void k_best_from_fit(GenArgs a) {
+  const int run = blockIdx.y;
+  unsigned long long best = ~0ull;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < a.NP; i += gridDim.x * 256)
+    best = min(best, fit_key(a.fit_cur[(size_t)run * a.NP + i], i));
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long o =
+        ((unsigned long long)__shfl_xor((unsigned)(best >> 32), m, 64) << 32) |
+        (unsigned long long)__shfl_xor((unsigned)best, m, 64);
+    best = min(best, o);
+  }
+  if ((threadIdx.x % 64) == 0) atomicMin(&a.best_key[run], best);
+}
+
+// Runs whose current best is already <= target hit at generation `gen`.
+__global__ void k_hit_check(GenArgs a, unsigned long long target_key) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < a.runs;
+       r += gridDim.x * blockDim.x) {
+    if ((a.best_key[r] >> 32) <= (target_key >> 32) &&
+        a.best_key[r] != ~0ull) {
+      const unsigned long long old = atomicMin(&a.hit_gen[r],
+                                               (unsigned long long)a.gen);
+      if (old == kNoHit) atomicAdd(a.done, 1u);
+    }
+  }
+}
+
+// Draws of generation a.gen: idx4 [runs][NP][4], mask [runs][NP][ceil(D/32)].
+__global__ __launch_bounds__(256) void k_debug_draws(GenArgs a, int* idx4,
+                                                     uint32_t* mask) {
+  const int nw = (a.D + 31) / 32;
+  const size_t total = (size_t)a.runs * a.NP * (size_t)(nw + 1);
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const size_t g = t / (nw + 1);
+    const int wsel = (int)(t % (nw + 1));
+    const int run = (int)(g / a.NP), i = (int)(g % a.NP);
+    const Donors d = pick_donors((uint32_t)run, a.gen, i, a.NP, a.D, a.key_lo,
+                                 a.key_hi);
+    if (wsel == nw) {
+      if (idx4) {
+        idx4[g * 4 + 0] = d.r1;
+        idx4[g * 4 + 1] = d.r2;
+        idx4[g * 4 + 2] = d.r3;
+        idx4[g * 4 + 3] = d.jrand;
+      }
+      continue;
+    }
+    if (!mask) continue;
+    uint32_t word = 0;
+    for (int qq = 0; qq < 8; ++qq) {
+      const int q = wsel * 8 + qq;
+      if (4 * q >= a.D) break;
+      const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen, (uint32_t)i,
+                                  (uint32_t)q, a.key_lo, a.key_hi);
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * q + b;
+        if (j < a.D && take_mutant(w.w[b], j, d.jrand, a.cr_threshold))
+          word |= 1u << (j % 32);
+      }
+    }
+    mask[g * nw + wsel] = word;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+namespace {
+
+int grid_for(size_t work, int per_block) {
+  size_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (1u << 20)) b = 1u << 20;
+  return (int)b;
+}
+
+template <int LPI, int ITER, bool EVAL>
+hipError_t launch_sep_t(const GenArgs& a, hipStream_t s) {
+  constexpr int IPB = 256 / LPI;
+  const int blocks = (a.nrows + IPB - 1) / IPB;
+  hipLaunchKernelGGL((k_sep<LPI, ITER, EVAL>), dim3(blocks), dim3(256), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <bool EVAL>
+hipError_t launch_sep_e(const GenArgs& a, hipStream_t s) {
+  const int nq = (a.D + 3) / 4;
+  if (nq <= 4) return launch_sep_t<4, 1, EVAL>(a, s);
+  if (nq <= 8) return launch_sep_t<8, 1, EVAL>(a, s);
+  if (nq <= 16) return launch_sep_t<16, 1, EVAL>(a, s);
+  if (nq <= 32) return launch_sep_t<32, 1, EVAL>(a, s);
+  if (nq <= 64) return launch_sep_t<64, 1, EVAL>(a, s);
+  if (nq <= 128) return launch_sep_t<64, 2, EVAL>(a, s);
+  if (nq <= 256) return launch_sep_t<64, 4, EVAL>(a, s);
+  if (nq <= 512) return launch_sep_t<64, 8, EVAL>(a, s);
+  if (nq <= 1024) return launch_sep_t<64, 16, EVAL>(a, s);
+  return hipErrorInvalidValue;
+}
+
+template <class P, bool EVAL>
+hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
+  const size_t lds = rot_lds_bytes<P>(a.dpad);
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_rot<P, EVAL>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  int blocks;
+  if (EVAL) {
+    blocks = (a.nrows + P::BM - 1) / P::BM;
+  } else {
+    blocks = a.runs * ((a.NP + P::BM - 1) / P::BM);
+  }
+  hipLaunchKernelGGL((k_rot<P, EVAL>), dim3(blocks), dim3(kRotThreads), lds, s,
+                     a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t rot_lds_bytes_host(int prec, int dpad) {
+  return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16>(dpad)
+                           : rot_lds_bytes<PrecF32>(dpad);
+}
+
+bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
+
+hipError_t launch_generation(const GenArgs& a, int kind, int prec,
+                             hipStream_t s) {
+  if (kind == kObjSphere) return launch_sep_e<false>(a, s);
+  return prec == kPrecBF16 ? launch_rot_t<PrecBF16, false>(a, s)
+                           : launch_rot_t<PrecF32, false>(a, s);
+}
+
+hipError_t launch_eval(const GenArgs& a, int kind, int prec, hipStream_t s) {
+  if (kind == kObjSphere) return launch_sep_e<true>(a, s);
+  return prec == kPrecBF16 ? launch_rot_t<PrecBF16, true>(a, s)
+                           : launch_rot_t<PrecF32, true>(a, s);
+}
+
+hipError_t launch_init(const GenArgs& a, hipStream_t s) {
+  const size_t work = (size_t)a.nrows * ((a.D + 3) / 4);
+  hipLaunchKernelGGL(k_init, dim3(grid_for(work, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const float* o, const float* R, int ldr, int D,
+                       int dpad, int kind, int prec, float* o_pad, void* rop,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_shift, dim3(grid_for(dpad, 256)), dim3(256), 0, s,
+                     o, D, dpad, o_pad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || kind != kObjRotOsc) return e;
+  const size_t total = (size_t)dpad * dpad;
+  if (prec == kPrecBF16) {
+    hipLaunchKernelGGL(k_prep_rot_bf16, dim3(grid_for(total, 256)), dim3(256),
+                       0, s, R, ldr, D, dpad, reinterpret_cast<__bf16*>(rop));
+  } else {
+    hipLaunchKernelGGL(k_prep_rot_f32, dim3(grid_for(total, 256)), dim3(256),
+                       0, s, R, ldr, D, dpad, reinterpret_cast<float*>(rop));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_reset(const GenArgs& a, bool reset_accepted,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reset, dim3(grid_for(a.runs, 256)), dim3(256), 0,
+                     s, a, reset_accepted ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_from_fit(const GenArgs& a, hipStream_t s) {
+  const int bx = grid_for(a.NP, 256) > 64 ? 64 : grid_for(a.NP, 256);
+  hipLaunchKernelGGL(k_best_from_fit, dim3(bx, a.runs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_check(const GenArgs& a, unsigned long long target_key,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_hit_check, dim3(grid_for(a.runs, 256)), dim3(256), 0,
+                     s, a, target_key);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_draws(const GenArgs& a, int* idx4, uint32_t* mask,
+                              hipStream_t s) {
+  const size_t work = (size_t)a.runs * a.NP * (size_t)((a.D + 31) / 32 + 1);
+  hipLaunchKernelGGL(k_debug_draws, dim3(grid_for(work, 256)), dim3(256), 0, s,
+                     a, idx4, mask);
+  return hipGetLastError();
+}
+
+}  // namespace de

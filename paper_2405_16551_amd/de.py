@@ -1,0 +1,295 @@
+"""Python binding of libde.so (the C ABI declared in include/de.h).
+
+Argument marshalling only: every step of DE runs in the library's HIP
+kernels.  The ``de_*`` functions mirror the C entry points one to one;
+``DifferentialEvolution`` is a convenience owner of the caller-side device
+buffers, allocated with PyTorch (device memory and streams are all PyTorch
+is used for).
+
+The library must have been built (``python -m paper_2405_16551_amd.build``);
+importing this module without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libde.so")
+
+DE_OK, DE_E_INVAL, DE_E_NOMEM, DE_E_DEVICE, DE_E_STATE, DE_E_UNSUPPORTED = range(6)
+DE_OBJ_SPHERE, DE_OBJ_ROT_OSC = 0, 1
+DE_GEMM_FP32, DE_GEMM_BF16 = 0, 1
+
+_KINDS = {"sphere": DE_OBJ_SPHERE, "rot_osc": DE_OBJ_ROT_OSC}
+_PRECS = {"fp32": DE_GEMM_FP32, "bf16": DE_GEMM_BF16}
+
+
+class de_params(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_int32), ("NP", ctypes.c_int32),
+                ("D", ctypes.c_int32), ("F", ctypes.c_float),
+                ("CR", ctypes.c_float), ("lo", ctypes.c_float),
+                ("hi", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class de_objective(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("gemm_prec", ctypes.c_int32),
+                ("ldr", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("o", ctypes.c_void_p), ("R", ctypes.c_void_p)]
+
+
+class de_buffers(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_void_p * 2), ("fit", ctypes.c_void_p * 2),
+                ("ldx", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ("de_abi_version", "de_strerror", "de_workspace_bytes",
+           "de_init_population", "de_generation", "de_evolve", "de_best",
+           "de_get_generation", "de_read_stats", "de_load_population",
+           "de_eval", "de_debug_draws", "de_destroy")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_2405_16551_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    st = ctypes.c_int
+    lib.de_abi_version.restype = i32
+    lib.de_abi_version.argtypes = []
+    lib.de_strerror.restype = ctypes.c_char_p
+    lib.de_strerror.argtypes = [st]
+    lib.de_workspace_bytes.restype = st
+    lib.de_workspace_bytes.argtypes = [P(de_params), P(de_objective),
+                                       P(ctypes.c_size_t)]
+    lib.de_init_population.restype = st
+    lib.de_init_population.argtypes = [P(de_params), P(de_objective),
+                                       P(de_buffers), vp, P(vp)]
+    lib.de_generation.restype = st
+    lib.de_generation.argtypes = [vp, i32, vp]
+    lib.de_evolve.restype = st
+    lib.de_evolve.argtypes = [vp, i64, ctypes.c_double, i32, vp, P(i64),
+                              P(i64)]
+    lib.de_best.restype = st
+    lib.de_best.argtypes = [vp, i32, vp, P(ctypes.c_float),
+                            P(ctypes.c_double), P(i32)]
+    lib.de_get_generation.restype = st
+    lib.de_get_generation.argtypes = [vp, P(i64)]
+    lib.de_read_stats.restype = st
+    lib.de_read_stats.argtypes = [vp, vp, P(i64), P(ctypes.c_double)]
+    lib.de_load_population.restype = st
+    lib.de_load_population.argtypes = [vp, i64, vp]
+    lib.de_eval.restype = st
+    lib.de_eval.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.de_debug_draws.restype = st
+    lib.de_debug_draws.argtypes = [vp, i64, vp, vp, vp]
+    lib.de_destroy.restype = st
+    lib.de_destroy.argtypes = [vp]
+    return lib
+
+
+_lib = _load()
+
+
+class DEError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {de_strerror(status)} (status {status})")
+
+
+def _check(status: int, where: str):
+    if status != DE_OK:
+        raise DEError(status, where)
+
+
+# ---- one-to-one wrappers of the C entry points ---------------------------
+
+def de_abi_version() -> int:
+    return int(_lib.de_abi_version())
+
+
+def de_strerror(status: int) -> str:
+    return _lib.de_strerror(status).decode()
+
+
+def de_workspace_bytes(params: de_params, objective: de_objective) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib.de_workspace_bytes(ctypes.byref(params),
+                                   ctypes.byref(objective), ctypes.byref(n)),
+           "de_workspace_bytes")
+    return int(n.value)
+
+
+def de_init_population(params, objective, buffers, stream) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(_lib.de_init_population(ctypes.byref(params),
+                                   ctypes.byref(objective),
+                                   ctypes.byref(buffers), stream,
+                                   ctypes.byref(h)), "de_init_population")
+    return h
+
+
+def de_generation(handle, n_gens: int, stream):
+    _check(_lib.de_generation(handle, n_gens, stream), "de_generation")
+
+
+def de_evolve(handle, max_gens: int, target: float, check_every: int, stream,
+              runs: int):
+    done = ctypes.c_int64(0)
+    hits = (ctypes.c_int64 * runs)()
+    _check(_lib.de_evolve(handle, max_gens, target, check_every, stream,
+                          ctypes.byref(done), hits), "de_evolve")
+    return int(done.value), [int(v) for v in hits]
+
+
+def de_best(handle, run: int, stream, D: int):
+    x = (ctypes.c_float * D)()
+    f = ctypes.c_double(0)
+    idx = ctypes.c_int32(0)
+    _check(_lib.de_best(handle, run, stream, x, ctypes.byref(f),
+                        ctypes.byref(idx)), "de_best")
+    return list(x), float(f.value), int(idx.value)
+
+
+def de_get_generation(handle) -> int:
+    g = ctypes.c_int64(0)
+    _check(_lib.de_get_generation(handle, ctypes.byref(g)), "de_get_generation")
+    return int(g.value)
+
+
+def de_read_stats(handle, stream, runs: int):
+    acc = (ctypes.c_int64 * runs)()
+    best = (ctypes.c_double * runs)()
+    _check(_lib.de_read_stats(handle, stream, acc, best), "de_read_stats")
+    return [int(v) for v in acc], [float(v) for v in best]
+
+
+def de_load_population(handle, gen: int, stream):
+    _check(_lib.de_load_population(handle, gen, stream), "de_load_population")
+
+
+def de_eval(handle, x_ptr: int, n: int, ldx: int, f_ptr: int, stream):
+    _check(_lib.de_eval(handle, x_ptr, n, ldx, f_ptr, stream), "de_eval")
+
+
+def de_debug_draws(handle, gen: int, idx4_ptr, mask_ptr, stream):
+    _check(_lib.de_debug_draws(handle, gen, idx4_ptr, mask_ptr, stream),
+           "de_debug_draws")
+
+
+def de_destroy(handle):
+    _check(_lib.de_destroy(handle), "de_destroy")
+
+
+# ---- owner of the caller-side buffers --------------------------------------
+
+class DifferentialEvolution:
+    """Device buffers (PyTorch) plus a library handle for one problem.
+
+    ``o`` (D floats) and, for 'rot_osc', ``R`` (D x D, row-major, z = R y)
+    may be NumPy arrays or tensors; they are copied to the device.
+    """
+
+    def __init__(self, *, runs, NP, D, F, CR, lo=-100.0, hi=100.0, seed=1,
+                 kind="sphere", o, R=None, gemm_prec="bf16", ldx=None,
+                 device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.runs, self.NP, self.D = int(runs), int(NP), int(D)
+        self.kind = kind
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ldx = int(ldx) if ldx is not None else (self.D + 3) // 4 * 4
+        dev = self.device
+        self.o = torch.as_tensor(o, dtype=torch.float32).to(dev).contiguous()
+        self.R = None
+        if kind == "rot_osc":
+            self.R = torch.as_tensor(R, dtype=torch.float32).to(dev).contiguous()
+        self.params = de_params(self.runs, self.NP, self.D, float(F), float(CR),
+                                float(lo), float(hi), int(seed))
+        self.objective = de_objective(
+            _KINDS[kind], _PRECS[gemm_prec], self.D, 0, self.o.data_ptr(),
+            self.R.data_ptr() if self.R is not None else None)
+        wbytes = de_workspace_bytes(self.params, self.objective)
+        rows = self.runs * self.NP
+        self.pop = [torch.zeros(rows * self.ldx, dtype=torch.float32, device=dev)
+                    for _ in range(2)]
+        self.fit = [torch.zeros(rows, dtype=torch.float32, device=dev)
+                    for _ in range(2)]
+        self.work = torch.zeros(wbytes + 256, dtype=torch.uint8, device=dev)
+        wptr = (self.work.data_ptr() + 255) // 256 * 256
+        self.buffers = de_buffers(
+            (ctypes.c_void_p * 2)(self.pop[0].data_ptr(), self.pop[1].data_ptr()),
+            (ctypes.c_void_p * 2)(self.fit[0].data_ptr(), self.fit[1].data_ptr()),
+            self.ldx, 0, wptr, wbytes)
+        self.handle = de_init_population(self.params, self.objective,
+                                         self.buffers, self._s())
+
+    def _s(self):
+        return self.stream.cuda_stream
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            de_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def gen(self) -> int:
+        return de_get_generation(self.handle)
+
+    def generation(self, n: int = 1):
+        de_generation(self.handle, n, self._s())
+
+    def evolve(self, max_gens: int, target: float = 1e-8, check_every: int = 50):
+        return de_evolve(self.handle, max_gens, target, check_every, self._s(),
+                         self.runs)
+
+    def best(self, run: int = 0):
+        return de_best(self.handle, run, self._s(), self.D)
+
+    def stats(self):
+        return de_read_stats(self.handle, self._s(), self.runs)
+
+    def population(self, gen=None):
+        """View [runs, NP, D] of pop[gen & 1] (current generation by default)."""
+        g = self.gen if gen is None else gen
+        return self.pop[g & 1].view(self.runs, self.NP, self.ldx)[:, :, :self.D]
+
+    def fitness(self, gen=None):
+        g = self.gen if gen is None else gen
+        return self.fit[g & 1].view(self.runs, self.NP)
+
+    def load_population(self, pop, gen: int):
+        """Write pop [runs, NP, D] as generation `gen` and re-evaluate it."""
+        self.pop[gen & 1].view(self.runs, self.NP, self.ldx)[:, :, :self.D].copy_(
+            self.torch.as_tensor(pop, dtype=self.torch.float32))
+        de_load_population(self.handle, gen, self._s())
+
+    def eval(self, x):
+        """Objective of rows x [n, D] (through the library's kernels)."""
+        torch = self.torch
+        x = torch.as_tensor(x, dtype=torch.float32).to(self.device)
+        n = x.shape[0]
+        xp = torch.zeros((n, self.ldx), dtype=torch.float32, device=self.device)
+        xp[:, :self.D] = x
+        f = torch.empty(n, dtype=torch.float32, device=self.device)
+        de_eval(self.handle, xp.data_ptr(), n, self.ldx, f.data_ptr(), self._s())
+        return f
+
+    def debug_draws(self, gen: int):
+        torch = self.torch
+        idx = torch.empty((self.runs, self.NP, 4), dtype=torch.int32, device=self.device)
+        nw = (self.D + 31) // 32
+        mask = torch.empty((self.runs, self.NP, nw), dtype=torch.int32, device=self.device)
+        de_debug_draws(self.handle, gen, idx.data_ptr(), mask.data_ptr(), self._s())
+        return idx, mask

@@ -1,0 +1,177 @@
+"""C-ABI boundary checks that need no GPU: exported symbols, version,
+argument validation (always synchronous and before any device call),
+handle-state errors, and the separation of the product from the oracle."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2405_16551_amd.de as d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "de.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return re.findall(r"DE_API\s+[\w\s\*]+?\b(de_\w+)\s*\(", src)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) == 13
+    assert set(names) == set(d.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", d.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for n in names:
+        assert n in exported, n
+        assert hasattr(d._lib, n)
+    # nothing else leaks from the library's C++ internals
+    assert {n for n in exported if n.startswith("de_")} == set(names)
+
+
+def test_abi_version_matches_header():
+    m = re.search(r"#define DE_ABI_VERSION (\d+)", open(HEADER).read())
+    assert d.de_abi_version() == int(m.group(1))
+
+
+def test_strerror_covers_every_status():
+    for s in range(6):
+        assert d.de_strerror(s)
+    assert d.de_strerror(99) == "unknown status"
+
+
+def P(**kw):
+    base = dict(runs=16, NP=1024, D=1000, F=0.5, CR=0.9, lo=-100.0, hi=100.0,
+                seed=1)
+    base.update(kw)
+    return d.de_params(*[base[k] for k in ("runs", "NP", "D", "F", "CR", "lo",
+                                           "hi", "seed")])
+
+
+def O(kind=1, prec=1, ldr=1000, reserved=0, o=256, R=256):
+    return d.de_objective(kind, prec, ldr, reserved, o, R)
+
+
+def ws_status(p, o):
+    n = ctypes.c_size_t(0)
+    return d._lib.de_workspace_bytes(ctypes.byref(p), ctypes.byref(o),
+                                     ctypes.byref(n)), n.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(runs=0), dict(runs=1 << 24), dict(NP=3), dict(NP=-5), dict(D=0),
+    dict(F=0.0), dict(F=-0.5), dict(F=math.nan), dict(F=math.inf),
+    dict(CR=-0.01), dict(CR=1.01), dict(CR=math.nan), dict(lo=100.0),
+    dict(lo=200.0), dict(lo=-math.inf), dict(hi=math.nan),
+    dict(lo=-3e38, hi=3e38), dict(runs=1 << 20, NP=1 << 12)])
+def test_invalid_params_rejected(kw):
+    assert ws_status(P(**kw), O())[0] == d.DE_E_INVAL
+
+
+@pytest.mark.parametrize("okw", [
+    dict(kind=2), dict(kind=-1), dict(prec=2), dict(reserved=1), dict(o=None),
+    dict(R=None), dict(ldr=999), dict(o=258)])
+def test_invalid_objective_rejected(okw):
+    assert ws_status(P(), O(**okw))[0] == d.DE_E_INVAL
+
+
+def test_sphere_ignores_rotation_fields():
+    st, n = ws_status(P(), O(kind=0, prec=7, ldr=0, R=None))
+    assert st == d.DE_OK and n > 0
+
+
+def test_unsupported_sizes():
+    assert ws_status(P(D=5000), O(ldr=5000))[0] == d.DE_E_UNSUPPORTED
+    assert ws_status(P(D=5000), O(kind=0))[0] == d.DE_E_UNSUPPORTED
+    assert ws_status(P(D=4096), O(kind=0))[0] == d.DE_OK
+    assert ws_status(P(D=1088), O(ldr=1088))[0] == d.DE_OK
+
+
+def test_workspace_bytes_layout():
+    st, sep = ws_status(P(), O(kind=0))
+    st2, bf = ws_status(P(), O(prec=1))
+    st3, f32 = ws_status(P(), O(prec=0))
+    assert st == st2 == st3 == d.DE_OK
+    assert sep % 256 == 0 and bf % 256 == 0
+    # rotated adds R in the operand layout, D padded to 1024
+    assert bf - sep == 1024 * 1024 * 2
+    assert f32 - sep == 1024 * 1024 * 4
+    assert d.de_workspace_bytes(P(), O(kind=0)) == sep
+
+
+def _bufs(**kw):
+    base = dict(pop0=1 << 20, pop1=2 << 20, fit0=3 << 20, fit1=4 << 20,
+                ldx=1000, reserved=0, work=5 << 20, work_bytes=1 << 30)
+    base.update(kw)
+    return d.de_buffers((ctypes.c_void_p * 2)(base["pop0"], base["pop1"]),
+                        (ctypes.c_void_p * 2)(base["fit0"], base["fit1"]),
+                        base["ldx"], base["reserved"], base["work"],
+                        base["work_bytes"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(pop0=None), dict(pop1=(2 << 20) + 4), dict(pop1=1 << 20),
+    dict(fit1=3 << 20), dict(fit0=None), dict(ldx=999), dict(ldx=1002),
+    dict(reserved=1), dict(work=None), dict(work=(5 << 20) + 64),
+    dict(work_bytes=1024)])
+def test_invalid_buffers_rejected_before_any_launch(kw):
+    h = ctypes.c_void_p()
+    st = d._lib.de_init_population(ctypes.byref(P()), ctypes.byref(O()),
+                                   ctypes.byref(_bufs(**kw)), None,
+                                   ctypes.byref(h))
+    assert st == d.DE_E_INVAL
+    assert h.value is None
+
+
+def test_null_out_pointer_rejected():
+    st = d._lib.de_init_population(ctypes.byref(P()), ctypes.byref(O()),
+                                   ctypes.byref(_bufs()), None, None)
+    assert st == d.DE_E_INVAL
+
+
+def test_calls_without_a_live_handle():
+    lib = d._lib
+    i64 = ctypes.c_int64(0)
+    dbl = ctypes.c_double(0)
+    bogus = ctypes.c_void_p(0x12345670)
+    for h in (None, bogus):
+        assert lib.de_generation(h, 1, None) == d.DE_E_STATE
+        assert lib.de_evolve(h, 10, 1e-8, 1, None, ctypes.byref(i64),
+                             None) == d.DE_E_STATE
+        assert lib.de_best(h, 0, None, None, ctypes.byref(dbl),
+                           None) == d.DE_E_STATE
+        assert lib.de_get_generation(h, ctypes.byref(i64)) == d.DE_E_STATE
+        assert lib.de_read_stats(h, None, None, None) == d.DE_E_STATE
+        assert lib.de_load_population(h, 0, None) == d.DE_E_STATE
+        assert lib.de_eval(h, 16, 1, 4, 16, None) == d.DE_E_STATE
+        assert lib.de_debug_draws(h, 0, None, None, None) == d.DE_E_STATE
+    assert lib.de_destroy(None) == d.DE_OK
+    assert lib.de_destroy(bogus) == d.DE_E_STATE
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    monkeypatch.setattr(d, "LIB_PATH", "/nonexistent/libde.so")
+    with pytest.raises(ImportError):
+        d._load()
+
+
+def test_product_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2405_16551_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", src,
+                                     re.M), fn
+                assert "liboracle" not in src and "de_oracle" not in src, fn
+    # and the oracle never touches the product
+    for fn in os.listdir(os.path.join(ROOT, "oracle")):
+        if fn.endswith((".py", ".c", ".h")):
+            src = open(os.path.join(ROOT, "oracle", fn)).read()
+            assert "paper_2405_16551_amd" not in src, fn
+            assert "de_device" not in src and "libde" not in src, fn

@@ -1,0 +1,358 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (from the method's definition, Section 2 of arXiv 2405.16551, and the
+arithmetic of each path):
+  * integer work (donor indices, j_rand, crossover decisions) and the initial
+    population: bit-exact;
+  * one generation from a shared FP32 population: trial coordinates within
+    one rounding of the FP32 fused multiply-add, fitness within 1e-5
+    relative (FP32 paths), selection identical except near-ties below that
+    tolerance;
+  * BF16 rotation GEMM: the per-result error against FP64 is measured and
+    bounded (see test_bf16_error_is_stated);
+  * whole runs: best-fitness distributions over 30 runs match the oracle's
+    under the paper's rank score (Mann-Whitney U) and KS, floored at the
+    1e-8 success threshold of Section 7.3.4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import de_stats
+from tests.gpu_helpers import (FP32_RTOL, HI, LO, compare_generation, host,
+                               make_de, okind)
+
+pytestmark = pytest.mark.gpu
+
+BF16_RTOL = 2e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU (run with -m 'not gpu' on CPU)")
+    import paper_2405_16551_amd.de as de  # noqa: F401  (fails if not built)
+    yield
+
+
+# ---------------------------------------------------------------------------
+# Initialisation and draws: bit-exact.
+
+@pytest.mark.parametrize("runs,NP,D,ldx", [(1, 64, 10, None), (3, 37, 13, 20),
+                                           (2, 5, 1, None), (2, 130, 1000, None)])
+def test_init_population_bit_exact(runs, NP, D, ldx):
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=11, ldx=ldx)
+    got = host(de.population(0))
+    want = oracle.init_population(runs, NP, D, LO, HI, 11).astype(np.float32)
+    np.testing.assert_array_equal(got, want)
+    f = host(de.fitness(0))
+    fo = oracle.objective_batch(oracle.OBJ_SPHERE, got.astype(np.float64).reshape(-1, D), o)
+    np.testing.assert_allclose(f.ravel(), fo, rtol=FP32_RTOL)
+
+
+@pytest.mark.parametrize("runs,NP,D,CR", [(2, 4, 3, 0.5), (3, 50, 37, 0.9),
+                                          (1, 1024, 1000, 0.3), (2, 33, 64, 0.0),
+                                          (1, 9, 70, 1.0)])
+def test_debug_draws_bit_exact(runs, NP, D, CR):
+    de, o, R = make_de(runs=runs, NP=NP, D=D, CR=CR, seed=7)
+    nw = (D + 31) // 32
+    for gen in (0, 1, 12345):
+        idx, mask = de.debug_draws(gen)
+        idx, mask = host(idx), host(mask).view(np.uint32)
+        rows = [(r, i) for r in range(runs) for i in range(NP)]
+        if len(rows) > 200:
+            rows = [rows[k] for k in np.random.default_rng(gen).choice(
+                len(rows), 200, replace=False)]
+        for r, i in rows:
+            want = oracle.draw_indices(7, r, gen, i, NP, D)
+            assert tuple(idx[r, i]) == want
+            bits = np.zeros(nw, dtype=np.uint32)
+            for j in range(D):
+                if oracle.take_mutant(7, r, gen, i, j, want[3], CR):
+                    bits[j // 32] |= np.uint32(1 << (j % 32))
+            np.testing.assert_array_equal(mask[r, i], bits)
+
+
+# ---------------------------------------------------------------------------
+# One generation from a shared FP32 population.
+
+@pytest.mark.parametrize("kind,prec,runs,NP,D,CR", [
+    ("sphere", "fp32", 3, 100, 37, 0.9),
+    ("sphere", "fp32", 1, 64, 10, 0.9),
+    ("sphere", "fp32", 2, 70, 1000, 0.9),
+    ("sphere", "fp32", 2, 4, 1, 0.5),
+    ("rot_osc", "fp32", 2, 70, 100, 0.9),
+    ("rot_osc", "fp32", 1, 40, 13, 0.3),
+    ("rot_osc", "fp32", 1, 65, 250, 0.9),
+])
+def test_one_generation_matches_oracle(kind, prec, runs, NP, D, CR):
+    de, o, R = make_de(runs=runs, NP=NP, D=D, CR=CR, seed=5, kind=kind,
+                       gemm_prec=prec)
+    # a few generations in, so that selection is not trivial
+    de.generation(3)
+    g = de.gen
+    pop32 = host(de.population()).copy()
+    fit_prev = host(de.fitness()).copy()
+    de.generation(1)
+    n, ties = compare_generation(host(de.population()), host(de.fitness()),
+                                 pop32, fit_prev, F=0.5, CR=CR, seed=5, gen=g,
+                                 kind=okind(kind), o=o, R=R, f_rtol=FP32_RTOL)
+    assert ties <= max(2, n // 50)
+
+
+def test_one_generation_bf16_gemm():
+    runs, NP, D = 2, 70, 100
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=5, kind="rot_osc",
+                       gemm_prec="bf16")
+    de.generation(2)
+    g = de.gen
+    pop32 = host(de.population()).copy()
+    fit_prev = host(de.fitness()).copy()
+    de.generation(1)
+    n, ties = compare_generation(host(de.population()), host(de.fitness()),
+                                 pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
+                                 kind=oracle.OBJ_ROT_OSC, o=o, R=R,
+                                 f_rtol=BF16_RTOL)
+    assert ties <= n // 10
+
+
+# ---------------------------------------------------------------------------
+# Objective evaluation through the generation kernels' arithmetic.
+
+@pytest.mark.parametrize("kind,prec,D,n,rtol", [
+    ("sphere", "fp32", 10, 130, FP32_RTOL),
+    ("sphere", "fp32", 1000, 70, FP32_RTOL),
+    ("rot_osc", "fp32", 100, 130, FP32_RTOL),
+    ("rot_osc", "fp32", 1000, 70, FP32_RTOL),
+    ("rot_osc", "bf16", 100, 130, BF16_RTOL),
+    ("rot_osc", "bf16", 1000, 70, BF16_RTOL),
+    ("rot_osc", "bf16", 7, 3, BF16_RTOL),
+])
+def test_eval_matches_oracle(kind, prec, D, n, rtol):
+    de, o, R = make_de(runs=1, NP=8, D=D, kind=kind, gemm_prec=prec)
+    rng = np.random.default_rng(D + n)
+    X = rng.uniform(LO, HI, (n, D)).astype(np.float32)
+    X[0] = o  # the optimum: f = 0 exactly
+    X[1] = o + np.float32(1e-3)  # near the optimum: small, still relative
+    f = host(de.eval(X)).astype(np.float64)
+    fo = oracle.objective_batch(okind(kind), X.astype(np.float64), o, R)
+    assert f[0] == 0.0
+    np.testing.assert_allclose(f, fo, rtol=rtol, atol=0)
+
+
+def test_bf16_error_is_stated():
+    # per-result relative error of the BF16 rotation GEMM against FP64, at
+    # the metric's dimension D = 1000: typical ~1e-4, bounded by BF16_RTOL
+    de, o, R = make_de(runs=1, NP=8, D=1000, kind="rot_osc", gemm_prec="bf16")
+    rng = np.random.default_rng(3)
+    X = rng.uniform(LO, HI, (256, 1000)).astype(np.float32)
+    scale = np.logspace(-4, 0, 256)[:, None].astype(np.float32)
+    X = (o + (X - o) * scale).astype(np.float32)  # from near-optimum to far
+    f = host(de.eval(X)).astype(np.float64)
+    fo = oracle.objective_batch(oracle.OBJ_ROT_OSC, X.astype(np.float64), o, R,
+                                nthreads=8)
+    rel = np.abs(f - fo) / fo
+    print(f"BF16 GEMM f rel. error vs FP64: median {np.median(rel):.2e}, "
+          f"p99 {np.quantile(rel, 0.99):.2e}, max {rel.max():.2e}")
+    assert np.median(rel) < 5e-4
+    assert rel.max() < BF16_RTOL
+
+
+# ---------------------------------------------------------------------------
+# Multi-generation behaviour.
+
+def test_teacher_forced_trajectory_sphere():
+    runs, NP, D, G = 2, 64, 10, 400
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1)
+    checkpoints = {0, 1, 10, 100, 250, 399}
+    for g in range(G):
+        if g in checkpoints:
+            pop32 = host(de.population()).copy()
+            fit_prev = host(de.fitness()).copy()
+            de.generation(1)
+            compare_generation(host(de.population()), host(de.fitness()), pop32,
+                               fit_prev, F=0.5, CR=0.9, seed=1, gen=g,
+                               kind=oracle.OBJ_SPHERE, o=o, R=None,
+                               f_rtol=FP32_RTOL)
+        else:
+            de.generation(1)
+
+
+def test_invariants_every_generation():
+    runs, NP, D = 4, 32, 20
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=3, kind="rot_osc",
+                       gemm_prec="bf16", CR=0.5)
+    prev_acc, prev_best = de.stats()
+    for _ in range(150):
+        de.generation(1)
+        pop = host(de.population())
+        assert pop.min() >= LO and pop.max() <= HI
+        acc, best = de.stats()
+        for r in range(runs):
+            assert 0 <= acc[r] - prev_acc[r] <= NP
+            assert best[r] <= prev_best[r]
+            assert best[r] == host(de.fitness())[r].min()
+        prev_acc, prev_best = acc, best
+
+
+def test_generation_split_does_not_matter():
+    a, _, _ = make_de(runs=2, NP=40, D=30, seed=9, kind="rot_osc")
+    b, _, _ = make_de(runs=2, NP=40, D=30, seed=9, kind="rot_osc")
+    a.generation(25)
+    for _ in range(25):
+        b.generation(1)
+    np.testing.assert_array_equal(host(a.population()), host(b.population()))
+    np.testing.assert_array_equal(host(a.fitness()), host(b.fitness()))
+
+
+@pytest.mark.parametrize("kind,prec", [("sphere", "fp32"), ("rot_osc", "bf16")])
+def test_checkpoint_restart_is_bit_exact(kind, prec):
+    a, _, _ = make_de(runs=2, NP=48, D=40, seed=4, kind=kind, gemm_prec=prec)
+    a.generation(60)
+    b, _, _ = make_de(runs=2, NP=48, D=40, seed=4, kind=kind, gemm_prec=prec)
+    b.generation(23)
+    snap = host(b.population()).copy()
+    c, _, _ = make_de(runs=2, NP=48, D=40, seed=4, kind=kind, gemm_prec=prec)
+    c.load_population(snap, 23)
+    c.generation(37)
+    np.testing.assert_array_equal(host(a.population()), host(c.population()))
+    np.testing.assert_array_equal(host(a.fitness()), host(c.fitness()))
+
+
+def test_evolve_stops_at_target_and_records_first_hit():
+    runs, NP, D = 3, 64, 10
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1)
+    ref, _, _ = make_de(runs=runs, NP=NP, D=D, seed=1)
+    gens_done, hits = de.evolve(2000, target=1e-8, check_every=64)
+    assert all(h > 0 for h in hits)
+    assert max(hits) <= gens_done < max(hits) + 64
+    # replay generation by generation: first generation with best <= 1e-8
+    first = [-1] * runs
+    for g in range(1, max(hits) + 1):
+        ref.generation(1)
+        _, best = ref.stats()
+        for r in range(runs):
+            if first[r] < 0 and best[r] <= 1e-8:
+                first[r] = g
+    assert first == hits
+    x, f, idx = de.best(0)
+    assert f <= 1e-8
+    np.testing.assert_allclose(x, o, atol=1e-3)
+
+
+def test_best_reports_lowest_value_lowest_index():
+    de, o, R = make_de(runs=2, NP=30, D=5, seed=2)
+    de.generation(40)
+    fit = host(de.fitness())
+    for r in range(2):
+        x, f, idx = de.best(r)
+        assert idx == int(np.argmin(fit[r]))
+        assert np.float32(f) == fit[r].min()
+        np.testing.assert_array_equal(np.array(x, np.float32),
+                                      host(de.population())[r, idx])
+
+
+# ---------------------------------------------------------------------------
+# Whole runs: distributions over 30 runs against the oracle.
+
+@pytest.mark.parametrize("kind,prec,NP,D,G,checks", [
+    ("sphere", "fp32", 64, 10, 400, (10, 100, 200, 400)),
+    ("rot_osc", "fp32", 48, 20, 300, (10, 100, 300)),
+    ("rot_osc", "bf16", 48, 20, 300, (10, 100, 300)),
+])
+def test_best_distribution_over_30_runs(kind, prec, NP, D, G, checks):
+    runs = 30
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1, kind=kind,
+                       gemm_prec=prec)
+    gpu = {}
+    done = 0
+    for c in checks:
+        de.generation(c - done)
+        done = c
+        gpu[c] = np.array(de.stats()[1])
+    res = oracle.run(runs=runs, NP=NP, D=D, F=0.5, CR=0.9, lo=LO, hi=HI,
+                     seed=1, kind=okind(kind), o=o, R=R, G=G, nthreads=8)
+    for c in checks:
+        ok, pu, pks = de_stats.same_distribution(gpu[c],
+                                                 res["best_trace"][:, c])
+        assert ok, (c, pu, pks, np.median(gpu[c]),
+                    np.median(res["best_trace"][:, c]))
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads: sampled rows the oracle computes one by one.
+
+def _sampled_generation_check(kind, prec, runs, NP, D, f_rtol, nsample=48):
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1, kind=kind,
+                       gemm_prec=prec)
+    de.generation(1)
+    g = de.gen
+    pop32 = host(de.population()).copy()
+    fit_prev = host(de.fitness()).copy()
+    de.generation(1)
+    pop_next, fit_next = host(de.population()), host(de.fitness())
+    rng = np.random.default_rng(0)
+    rows = [(int(rng.integers(runs)), int(rng.integers(NP)))
+            for _ in range(nsample)]
+    rows += [(0, 0), (runs - 1, NP - 1)]
+    kind_o = okind(kind)
+    flips = 0
+    for r, i in rows:
+        r1, r2, r3, jr = oracle.draw_indices(1, r, g, i, NP, D)
+        x = pop32[r, i].astype(np.float64)
+        m = np.clip(pop32[r, r1].astype(np.float64) + 0.5 *
+                    (pop32[r, r2].astype(np.float64) -
+                     pop32[r, r3].astype(np.float64)), LO, HI)
+        take = np.array([oracle.take_mutant(1, r, g, i, j, jr, 0.9)
+                         for j in range(D)])
+        u = np.where(take, m, x)
+        fu = oracle.objective(kind_o, u, o, R)
+        fx = oracle.objective(kind_o, x, o, R)
+        assert abs(fit_prev[r, i] - fx) <= f_rtol * fx
+        if abs(fu - fx) <= f_rtol * fx:
+            flips += 1
+            continue
+        if fu < fx:
+            tol = 2.0 ** -22 * (np.abs(pop32[r, r1]) + 0.5 * (
+                np.abs(pop32[r, r2]) + np.abs(pop32[r, r3]))) + 1e-30
+            assert (np.abs(pop_next[r, i] - u) <= tol).all()
+            assert abs(fit_next[r, i] - fu) <= f_rtol * fu
+        else:
+            np.testing.assert_array_equal(pop_next[r, i], pop32[r, i])
+    assert flips <= 2
+
+
+def test_full_size_separable_sampled():
+    _sampled_generation_check("sphere", "fp32", 16, 1024, 1000, FP32_RTOL)
+
+
+def test_full_size_rotated_bf16_sampled():
+    _sampled_generation_check("rot_osc", "bf16", 16, 1024, 1000, BF16_RTOL,
+                              nsample=24)
+
+
+def test_full_size_rotated_fp32_sampled():
+    _sampled_generation_check("rot_osc", "fp32", 16, 1024, 1000, FP32_RTOL,
+                              nsample=24)
+
+
+# ---------------------------------------------------------------------------
+# Error paths through the ABI on a live device.
+
+def test_destroyed_handle_and_bad_calls():
+    import paper_2405_16551_amd.de as d
+    de, o, R = make_de(runs=1, NP=8, D=4)
+    h = de.handle
+    with pytest.raises(d.DEError) as e:
+        d.de_generation(h, -1, de._s())
+    assert e.value.status == d.DE_E_INVAL
+    with pytest.raises(d.DEError) as e:
+        d.de_best(h, 1, de._s(), 4)
+    assert e.value.status == d.DE_E_INVAL
+    de.close()
+    with pytest.raises(d.DEError) as e:
+        d.de_generation(h, 1, 0)
+    assert e.value.status == d.DE_E_STATE
