@@ -29,7 +29,7 @@ struct Words4 {
 
 // One S-box round: two 32x32->64 products (v_mad_u64_u32 on CDNA), the
 // high halves mixed with the other two counter words and the round key.
-__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
+__host__ __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
                                              uint32_t& c2, uint32_t& c3,
                                              uint32_t k0, uint32_t k1) {
   const uint64_t pa = (uint64_t)kPhiloxMulA * c0;
@@ -42,7 +42,7 @@ __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
   c2 = n2;
 }
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
+__host__ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
                                                 uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -59,7 +59,7 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1,
 }
 
 // Draw block for (tag, run, gen, individual, group q).
-__device__ __forceinline__ Words4 draw_block(uint32_t tag, uint32_t run,
+__host__ __device__ __forceinline__ Words4 draw_block(uint32_t tag, uint32_t run,
                                              uint32_t gen, uint32_t indiv,
                                              uint32_t q, uint32_t key_lo,
                                              uint32_t key_hi) {
@@ -67,8 +67,8 @@ __device__ __forceinline__ Words4 draw_block(uint32_t tag, uint32_t run,
 }
 
 // Uniform integer in [0, n) from one 32-bit word: floor(w * n / 2^32).
-__device__ __forceinline__ int uniform_below(uint32_t w, uint32_t n) {
-  return (int)__umulhi(w, n);
+__host__ __device__ __forceinline__ int uniform_below(uint32_t w, uint32_t n) {
+  return (int)(((uint64_t)w * n) >> 32);
 }
 
 // Donor triple and j_rand of eq. 2 / eq. 3 for target i.  a, b, c are
@@ -79,7 +79,7 @@ struct Donors {
   int r1, r2, r3, jrand;
 };
 
-__device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t gen,
+__host__ __device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t gen,
                                               int i, int NP, int D,
                                               uint32_t key_lo,
                                               uint32_t key_hi) {
@@ -108,13 +108,13 @@ __device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t gen,
 
 // Crossover test of eq. 3 for coordinate j = 4q + b: rand_j = (w >> 8) 2^-24
 // and rand_j <= CR  <=>  (w >> 8) <= floor(CR 2^24) = cr_threshold.
-__device__ __forceinline__ bool take_mutant(uint32_t word, int j, int jrand,
+__host__ __device__ __forceinline__ bool take_mutant(uint32_t word, int j, int jrand,
                                             uint32_t cr_threshold) {
   return (j == jrand) || ((word >> 8) <= cr_threshold);
 }
 
 // Mutant coordinate of eq. 2 with clamping to the box; NaN passes through.
-__device__ __forceinline__ float mutant_coord(float x1, float x2, float x3,
+__host__ __device__ __forceinline__ float mutant_coord(float x1, float x2, float x3,
                                               float F, float lo, float hi) {
   float v = fmaf(F, x2 - x3, x1);
   v = v < lo ? lo : v;
@@ -125,10 +125,36 @@ __device__ __forceinline__ float mutant_coord(float x1, float x2, float x3,
 // Totally ordered 64-bit key: order-preserving image of the float in the high
 // half (NaN sorts above +inf), individual index in the low half, so
 // atomicMin yields the lowest value with ties to the lowest index.
-__device__ __forceinline__ unsigned long long fit_key(float f, int idx) {
-  const uint32_t b = __float_as_uint(f);
+__host__ __device__ __forceinline__ unsigned long long fit_key(float f, int idx) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, f);
   const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
   return ((unsigned long long)ord << 32) | (uint32_t)idx;
+}
+
+// sin^2(t), t in FP32.  t = k (pi/2) + r with |r| <= pi/4: k = rint(t 2/pi),
+// r by Cody-Waite reduction with pi/2 split into three FP32 parts (each
+// product k * part folded in with one FMA).  sin^2(t) = sin^2(r) for even k
+// and 1 - sin^2(r) for odd k.  sin^2(r) from its Taylor series
+// sum_{n>=1} (-1)^(n+1) 2^(2n-1) r^(2n) / (2n)!, six terms: the first
+// omitted term is below 4e-9 on |r| <= pi/4, under half an FP32 ulp of 0.5.
+__host__ __device__ __forceinline__ float sin_squared(float t) {
+  constexpr float kTwoOverPi = 0x1.45f306p-1f;
+  constexpr float kHalfPiA = 0x1.921fb6p+0f;
+  constexpr float kHalfPiB = -0x1.777a5cp-25f;
+  constexpr float kHalfPiC = -0x1.ee59dap-50f;
+  const float k = rintf(t * kTwoOverPi);
+  float r = fmaf(-k, kHalfPiA, t);
+  r = fmaf(-k, kHalfPiB, r);
+  r = fmaf(-k, kHalfPiC, r);
+  const float s = r * r;
+  float p = -2.0f / 467775.0f;
+  p = fmaf(p, s, 2.0f / 14175.0f);
+  p = fmaf(p, s, -1.0f / 315.0f);
+  p = fmaf(p, s, 2.0f / 45.0f);
+  p = fmaf(p, s, -1.0f / 3.0f);
+  p = fmaf(p, s, 1.0f);
+  p *= s;
+  return ((int)k & 1) ? 1.0f - p : p;
 }
 
 // Sum over aligned groups of `width` lanes (power of two <= 64) by
@@ -144,7 +170,7 @@ __device__ __forceinline__ float group_sum(float v) {
 // Block index remapping so that consecutive logical blocks land on the same
 // XCD (gfx950 dispatches block b to XCD b mod 8): logical block ranges, and
 // the donor rows they share, then stay in one XCD's L2.  Bijective for any n.
-__device__ __forceinline__ int xcd_logical_block(int b, int n) {
+__host__ __device__ __forceinline__ int xcd_logical_block(int b, int n) {
   constexpr int kXcd = 8;
   const int q = n / kXcd, r = n % kXcd;
   const int xcd = b % kXcd, k = b / kXcd;

@@ -190,9 +190,15 @@ __device__ __forceinline__ int lds_col(int k) {
   }
 }
 
+// One coordinate of the rotated oscillating objective: z^2 + sin^2(3z).
 __device__ __forceinline__ float osc_term(float z) {
-  const float s = sinf(3.0f * z);
-  return fmaf(z, z, s * s);
+  return fmaf(z, z, sin_squared(3.0f * z));
+}
+
+__device__ __forceinline__ void osc_accumulate(floatx16& part,
+                                               const floatx16& c) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part[r] += osc_term(c[r]);
 }
 
 template <class P, bool EVAL>
@@ -285,22 +291,12 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
   __syncthreads();
 
   // ---- phase 2: Z = Y R^T with the objective fused into the epilogue
+  // Accumulators c{m}{n}: 32x32 block (row block m, column block nb0 + n).
+  // Named values, not arrays, so that every index is static.
   const int nblk = dpad / 32;
-  float part[MB][16];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) part[mb][r] = 0.f;
-
+  floatx16 part0 = {}, part1 = {};
   for (int nb0 = wave * kNB; nb0 < nblk; nb0 += kRotWaves * kNB) {
-    floatx16 acc[MB][kNB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int t = 0; t < kNB; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[mb][t][r] = 0.f;
-
+    floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
     if constexpr (sizeof(T) == 2) {
       // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per block
       const bf16x8* rop = reinterpret_cast<const bf16x8*>(a.rop);
@@ -308,20 +304,17 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
       const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
       const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
       const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
-#pragma unroll 4
       for (int kb = 0; kb < kbn; ++kb) {
         const bf16x8 b0 = rb0[(size_t)kb * 64];
         const bf16x8 b1 = rb1[(size_t)kb * 64];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(
-              ar + (size_t)mb * 32 * stride + kb * 16);
-          acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0,
-                                                               acc[mb][0], 0,
-                                                               0, 0);
-          acc[mb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1,
-                                                               acc[mb][1], 0,
-                                                               0, 0);
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ar + kb * 16);
+        c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, c01, 0, 0, 0);
+        if constexpr (MB == 2) {
+          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(
+              ar + (size_t)32 * stride + kb * 16);
+          c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, c10, 0, 0, 0);
+          c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, c11, 0, 0, 0);
         }
       }
     } else {
@@ -332,39 +325,39 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
       const float4* rb1 = rb0 + (size_t)k8n * 64;
       const float* ar = reinterpret_cast<const float*>(At) +
                         (size_t)(lane % 32) * stride + 4 * (lane / 32);
-#pragma unroll 2
       for (int k8 = 0; k8 < k8n; ++k8) {
         const float4 b0 = rb0[(size_t)k8 * 64];
         const float4 b1 = rb1[(size_t)k8 * 64];
         const float4 av = *reinterpret_cast<const float4*>(ar + k8 * 8);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-              get(av, s), get(b0, s), acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-              get(av, s), get(b1, s), acc[0][1], 0, 0, 0);
-        }
+        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b0.x, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b1.x, c01, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b0.y, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b1.y, c01, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b0.z, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b1.z, c01, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b0.w, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b1.w, c01, 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int t = 0; t < kNB; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) part[mb][r] += osc_term(acc[mb][t][r]);
+    osc_accumulate(part0, c00);
+    osc_accumulate(part0, c01);
+    if constexpr (MB == 2) {
+      osc_accumulate(part1, c10);
+      osc_accumulate(part1, c11);
+    }
   }
   // 32x32 accumulator layout: register r of lane l holds row
   // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float s = group_sum<32>(part[mb][r]);
-      if ((lane % 32) == 0) {
-        const int row = mb * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        fpart[wave * BM + row] = s;
-      }
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+    const float s0 = group_sum<32>(part0[r]);
+    if ((lane % 32) == 0) fpart[wave * BM + row] = s0;
+    if constexpr (MB == 2) {
+      const float s1 = group_sum<32>(part1[r]);
+      if ((lane % 32) == 0) fpart[wave * BM + 32 + row] = s1;
     }
+  }
   __syncthreads();
 
   // ---- phase 3: selection and the next generation

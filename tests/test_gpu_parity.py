@@ -286,6 +286,7 @@ def test_best_distribution_over_30_runs(kind, prec, NP, D, G, checks):
 # Full-size workloads: sampled rows the oracle computes one by one.
 
 def _sampled_generation_check(kind, prec, runs, NP, D, f_rtol, nsample=48):
+    from tests.gpu_helpers import rounding_band, trial_atol
     de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1, kind=kind,
                        gemm_prec=prec)
     de.generation(1)
@@ -303,23 +304,24 @@ def _sampled_generation_check(kind, prec, runs, NP, D, f_rtol, nsample=48):
     for r, i in rows:
         r1, r2, r3, jr = oracle.draw_indices(1, r, g, i, NP, D)
         x = pop32[r, i].astype(np.float64)
-        m = np.clip(pop32[r, r1].astype(np.float64) + 0.5 *
-                    (pop32[r, r2].astype(np.float64) -
-                     pop32[r, r3].astype(np.float64)), LO, HI)
+        p1, p2, p3 = (pop32[r, k].astype(np.float64) for k in (r1, r2, r3))
+        m = np.clip(p1 + 0.5 * (p2 - p3), LO, HI)
         take = np.array([oracle.take_mutant(1, r, g, i, j, jr, 0.9)
                          for j in range(D)])
         u = np.where(take, m, x)
         fu = oracle.objective(kind_o, u, o, R)
         fx = oracle.objective(kind_o, x, o, R)
         assert abs(fit_prev[r, i] - fx) <= f_rtol * fx
-        if abs(fu - fx) <= f_rtol * fx:
+        tol = trial_atol(p1, p2, p3, 0.5)
+        band = f_rtol * max(fu, fx) + rounding_band(kind_o, u, o, R, tol)
+        if abs(fu - fx) <= band:
             flips += 1
             continue
         if fu < fx:
-            tol = 2.0 ** -22 * (np.abs(pop32[r, r1]) + 0.5 * (
-                np.abs(pop32[r, r2]) + np.abs(pop32[r, r3]))) + 1e-30
             assert (np.abs(pop_next[r, i] - u) <= tol).all()
-            assert abs(fit_next[r, i] - fu) <= f_rtol * fu
+            f_own = oracle.objective(kind_o, pop_next[r, i].astype(np.float64),
+                                     o, R)
+            assert abs(fit_next[r, i] - f_own) <= f_rtol * f_own
         else:
             np.testing.assert_array_equal(pop_next[r, i], pop32[r, i])
     assert flips <= 2
