@@ -113,6 +113,11 @@ typedef struct de_objective {
  *                   ldx >= D, ldx % 4 == 0, both pointers 16-byte aligned.
  *                   Generation g lives in pop[g & 1] (ping-pong).
  *   fit[0], fit[1]: runs * NP floats each, the objective of the matching row.
+ *                   Between calls the library owns the contents of both
+ *                   population buffers: a step may leave a row of the
+ *                   buffer it writes untouched when that buffer already
+ *                   holds the row's new value, so callers change populations
+ *                   only through de_load_population.
  *   work          : scratch of at least de_workspace_bytes() bytes,
  *                   256-byte aligned; holds per-run statistics and, for
  *                   rotated objectives, R in the GEMM operand layout.  Its

@@ -25,7 +25,7 @@ constexpr uint64_t kMagic = 0x4445'6d69'3335'3578ull;
 constexpr int64_t kGenLimit = int64_t(1) << 32;  // counter field is 32-bit
 
 struct Layout {
-  size_t best, hit, acc, done, opad, rop, total;
+  size_t best, hit, acc, done, changed, opad, rop, total;
 };
 
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
@@ -45,6 +45,7 @@ Layout layout_for(const de_params& p, int kind, int prec) {
   L.hit = take(8 * (size_t)p.runs);
   L.acc = take(8 * (size_t)p.runs);
   L.done = take(4);
+  L.changed = take((size_t)p.runs * p.NP);
   L.opad = take(4 * (size_t)dpad);
   L.rop = 0;
   if (kind == de::kObjRotOsc)
@@ -129,6 +130,7 @@ GenArgs base_args(const de_state* s) {
   a.hit_gen = reinterpret_cast<unsigned long long*>(s->work + s->L.hit);
   a.accepted = reinterpret_cast<unsigned long long*>(s->work + s->L.acc);
   a.done = reinterpret_cast<unsigned int*>(s->work + s->L.done);
+  a.changed = reinterpret_cast<unsigned char*>(s->work + s->L.changed);
   a.runs = s->p.runs;
   a.NP = s->p.NP;
   a.D = s->p.D;
@@ -155,6 +157,9 @@ de_status eval_current_and_reset(de_state* s, hipStream_t st) {
   de_status rc = from_hip(de::launch_eval(a, s->kind, s->prec, st));
   if (rc != DE_OK) return rc;
   rc = from_hip(de::launch_stats_reset(a, true, st));
+  if (rc != DE_OK) return rc;
+  // the other buffer's rows are unknown: the next step rewrites every row
+  rc = from_hip(de::launch_mark_changed(a, st));
   if (rc != DE_OK) return rc;
   a.fit_cur = s->fit[b];
   return from_hip(de::launch_best_from_fit(a, st));

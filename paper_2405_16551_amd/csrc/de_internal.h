@@ -24,12 +24,14 @@ struct GenArgs {
   unsigned long long* hit_gen;   // [runs] first generation with best <= target
   unsigned long long* accepted;  // [runs] accepted trials
   unsigned int* done;            // runs that have hit the target
+  unsigned char* changed;        // [runs*NP] row changed in the last step
   int runs, NP, D, ldx, dpad, nrows;
   float F, lo, hi, target;
   uint32_t cr_threshold, gen, key_lo, key_hi;
 };
 
 size_t rot_lds_bytes_host(int prec, int dpad);
+int rot_tile_rows(int prec, int dpad);
 bool sep_supported(int D);
 
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,
@@ -42,6 +44,7 @@ hipError_t launch_prep(const float* o, const float* R, int ldr, int D,
 hipError_t launch_stats_reset(const GenArgs& a, bool reset_accepted,
                               hipStream_t s);
 hipError_t launch_best_from_fit(const GenArgs& a, hipStream_t s);
+hipError_t launch_mark_changed(const GenArgs& a, hipStream_t s);
 hipError_t launch_hit_check(const GenArgs& a, unsigned long long target_key,
                             hipStream_t s);
 hipError_t launch_debug_draws(const GenArgs& a, int* idx4, uint32_t* mask,

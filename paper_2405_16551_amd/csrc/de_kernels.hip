@@ -17,6 +17,7 @@
 //           read from L2 in a fragment-major layout prepared once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "de_device.hpp"
 #include "de_internal.h"
@@ -132,49 +133,51 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
   }
   const float fx = a.fit_cur[g];
   const bool accept = f < fx;
-  float* nrow = a.pop_next + (size_t)g * a.ldx;
+  // a rejected row is rewritten only if the other buffer holds a stale copy
+  // (the row changed in the previous generation)
+  if (accept || a.changed[g] != 0) {
+    float* nrow = a.pop_next + (size_t)g * a.ldx;
 #pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const int j0 = 4 * (ln + it * LPI);
-    if (j0 < a.D) st4(nrow + j0, accept ? uv[it] : xv[it]);
+    for (int it = 0; it < ITER; ++it) {
+      const int j0 = 4 * (ln + it * LPI);
+      if (j0 < a.D) st4(nrow + j0, accept ? uv[it] : xv[it]);
+    }
   }
   if (ln == 0) {
     a.fit_next[g] = accept ? f : fx;
+    a.changed[g] = accept ? 1 : 0;
     if (accept) record_accept(a, run, i, f);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Rotated objective.  Tile of BM rows per 512-thread workgroup.
-//   phase 1: trial rows -> LDS A tile (y = u - o in the GEMM precision) and
-//            crossover bit planes; padding rows/columns are zero.
-//   phase 2: Z = Y R^T, 32x32 MFMA blocks, wave tile BM x 64 columns,
-//            epilogue z^2 + sin^2(3z) summed per row in registers.
-//   phase 3: row totals -> selection -> next generation rows, statistics.
+// Rotated objective.  Tile of BM trial rows per workgroup of NT threads.
+//   phase 1: donors of every row, then per row all target/donor loads in
+//            flight before the crossover draws; trial rows -> LDS A tile as
+//            y = u - o in the GEMM precision, crossover decisions -> bit
+//            planes; padding rows and columns are zero.
+//   phase 2: Z = Y R^T in 32x32 MFMA blocks, wave tile BM x 64 columns, R
+//            fragments prefetched four K-steps ahead from L2; the objective
+//            z^2 + sin^2(3z) is summed per row in registers.
+//   phase 3: row totals -> selection -> next generation rows (a rejected row
+//            is rewritten only if the other buffer holds a stale copy),
+//            statistics.
 struct PrecBF16 {
   using T = __bf16;
-  static constexpr int BM = 64;
-  static constexpr int MB = 2;  // 32-row MFMA blocks per tile
-  __host__ __device__ static constexpr int stride(int dpad) { return dpad + 8; }
+  static constexpr int kPad = 8;  // LDS row padding, elements
 };
 struct PrecF32 {
   using T = float;
-  static constexpr int BM = 32;
-  static constexpr int MB = 1;
-  __host__ __device__ static constexpr int stride(int dpad) { return dpad + 4; }
+  static constexpr int kPad = 4;
 };
 
-constexpr int kRotThreads = 512;
-constexpr int kRotWaves = kRotThreads / 64;
-constexpr int kNB = 2;  // 32-column MFMA blocks per wave per chunk
-
-template <class P>
+template <class P, int BM, int NT>
 __host__ __device__ constexpr size_t rot_lds_bytes(int dpad) {
   const int tq = (dpad / 4 + 63) / 64;
-  return (size_t)P::BM * P::stride(dpad) * sizeof(typename P::T)  // A tile
-         + (size_t)P::BM * tq * 4 * sizeof(unsigned long long)   // planes
-         + (size_t)P::BM * 4 * sizeof(int)                       // donors
-         + (size_t)kRotWaves * P::BM * sizeof(float);            // partials
+  return (size_t)BM * (dpad + P::kPad) * sizeof(typename P::T)  // A tile
+         + (size_t)BM * tq * 4 * sizeof(unsigned long long)     // planes
+         + (size_t)BM * 4 * sizeof(int)                         // donors
+         + (size_t)(NT / 64) * BM * sizeof(float);              // partials
 }
 
 // Position of coordinate k inside an LDS row.  BF16: natural order.  FP32:
@@ -201,13 +204,49 @@ __device__ __forceinline__ void osc_accumulate(floatx16& part,
   for (int r = 0; r < 16; ++r) part[r] += osc_term(c[r]);
 }
 
-template <class P, bool EVAL>
-__global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
+// One BF16 K-step (16) of the wave tile: rows 0-31 (and 32-63), columns of
+// two 32-wide blocks.
+template <int MB>
+__device__ __forceinline__ void bf16_step(const __bf16* ar, int stride, int kb,
+                                          bf16x8 b0, bf16x8 b1, floatx16& c00,
+                                          floatx16& c01, floatx16& c10,
+                                          floatx16& c11) {
+  const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ar + kb * 16);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, c01, 0, 0, 0);
+  if constexpr (MB == 2) {
+    const bf16x8 a1 =
+        *reinterpret_cast<const bf16x8*>(ar + (size_t)32 * stride + kb * 16);
+    c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, c10, 0, 0, 0);
+    c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, c11, 0, 0, 0);
+  }
+}
+
+// Four FP32 K-steps (8 coordinates) of the wave tile, rows 0-31.
+__device__ __forceinline__ void f32_step(const float* ar, int k8, float4 b0,
+                                         float4 b1, floatx16& c00,
+                                         floatx16& c01) {
+  const float4 av = *reinterpret_cast<const float4*>(ar + k8 * 8);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b0.x, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b1.x, c01, 0, 0, 0);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b0.y, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b1.y, c01, 0, 0, 0);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b0.z, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b1.z, c01, 0, 0, 0);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b0.w, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b1.w, c01, 0, 0, 0);
+}
+
+template <class P, int BM, int NT, bool EVAL>
+__global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
   using T = typename P::T;
-  constexpr int BM = P::BM, MB = P::MB;
+  constexpr int MB = BM / 32;
+  constexpr int kRotThreads = NT;
+  constexpr int kRotWaves = NT / 64;
+  static_assert(MB == 1 || (MB == 2 && sizeof(T) == 2), "tile shape");
   extern __shared__ __align__(16) char smem[];
   const int dpad = a.dpad;
-  const int stride = P::stride(dpad);
+  const int stride = dpad + P::kPad;
   const int tq = (dpad / 4 + 63) / 64;
   T* At = reinterpret_cast<T*>(smem);
   unsigned long long* planes = reinterpret_cast<unsigned long long*>(
@@ -230,6 +269,17 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
   const float* base = a.pop_cur + (EVAL ? 0 : (size_t)run * a.NP * a.ldx);
 
   // ---- phase 1: build the A tile
+  if (!EVAL) {
+    for (int rl = (int)threadIdx.x; rl < nvalid; rl += kRotThreads) {
+      const Donors d = pick_donors((uint32_t)run, a.gen, row0 + rl, a.NP, a.D,
+                                   a.key_lo, a.key_hi);
+      donors[rl * 4 + 0] = d.r1;
+      donors[rl * 4 + 1] = d.r2;
+      donors[rl * 4 + 2] = d.r3;
+      donors[rl * 4 + 3] = d.jrand;
+    }
+    __syncthreads();
+  }
   for (int rl = wave; rl < BM; rl += kRotWaves) {
     T* arow = At + (size_t)rl * stride;
     if (rl >= nvalid) {
@@ -238,52 +288,75 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
     }
     const int i = row0 + rl;
     const float* xrow = base + (size_t)i * a.ldx;
-    Donors d{0, 0, 0, 0};
     const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
+    int jrand = 0;
     if (!EVAL) {
-      d = pick_donors((uint32_t)run, a.gen, i, a.NP, a.D, a.key_lo, a.key_hi);
-      x1 = base + (size_t)d.r1 * a.ldx;
-      x2 = base + (size_t)d.r2 * a.ldx;
-      x3 = base + (size_t)d.r3 * a.ldx;
-      if (lane == 0) {
-        donors[rl * 4 + 0] = d.r1;
-        donors[rl * 4 + 1] = d.r2;
-        donors[rl * 4 + 2] = d.r3;
-        donors[rl * 4 + 3] = d.jrand;
-      }
+      x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
+      x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
+      x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+      jrand = donors[rl * 4 + 3];
     }
-    for (int t = 0; t < tq; ++t) {
-      const int q = lane + 64 * t, j0 = 4 * q;
-      uint32_t bits = 0;
-      float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (j0 < a.D) {
-        const float4 xv = ld4(xrow + j0);
-        const float4 u = EVAL ? xv
-                              : trial4(a, (uint32_t)run, i, q, d, x1, x2, x3,
-                                       xv, &bits);
-        const float4 ov = ld4(a.o + j0);
+    for (int t0 = 0; t0 < tq; t0 += 4) {
+      float4 xv[4], v1[4], v2[4], v3[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          set(y, b, (j0 + b < a.D) ? get(u, b) - get(ov, b) : 0.f);
-      }
-      if (j0 < dpad) {
-        if constexpr (sizeof(T) == 2) {
-          bf16x4 yb;
-          yb[0] = (__bf16)y.x;
-          yb[1] = (__bf16)y.y;
-          yb[2] = (__bf16)y.z;
-          yb[3] = (__bf16)y.w;
-          *reinterpret_cast<bf16x4*>(arow + j0) = yb;
-        } else {
-#pragma unroll
-          for (int b = 0; b < 4; ++b) arow[lds_col<P>(j0 + b)] = get(y, b);
+      for (int u = 0; u < 4; ++u) {
+        const int j0 = 4 * (lane + 64 * (t0 + u));
+        if (t0 + u < tq && j0 < a.D) {
+          xv[u] = ld4(xrow + j0);
+          if (!EVAL) {
+            v1[u] = ld4(x1 + j0);
+            v2[u] = ld4(x2 + j0);
+            v3[u] = ld4(x3 + j0);
+          }
         }
       }
-      if (!EVAL) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const unsigned long long m = __ballot((bits >> b) & 1u);
-          if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + u;
+        if (t >= tq) break;
+        const int q = lane + 64 * t, j0 = 4 * q;
+        uint32_t bits = 0;
+        float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j0 < a.D) {
+          float4 uu = xv[u];
+          if (!EVAL) {
+            const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen,
+                                        (uint32_t)i, (uint32_t)q, a.key_lo,
+                                        a.key_hi);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              if (j0 + b < a.D &&
+                  take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold)) {
+                set(uu, b, mutant_coord(get(v1[u], b), get(v2[u], b),
+                                        get(v3[u], b), a.F, a.lo, a.hi));
+                bits |= 1u << b;
+              }
+            }
+          }
+          const float4 ov = ld4(a.o + j0);
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            set(y, b, (j0 + b < a.D) ? get(uu, b) - get(ov, b) : 0.f);
+        }
+        if (j0 < dpad) {
+          if constexpr (sizeof(T) == 2) {
+            bf16x4 yb;
+            yb[0] = (__bf16)y.x;
+            yb[1] = (__bf16)y.y;
+            yb[2] = (__bf16)y.z;
+            yb[3] = (__bf16)y.w;
+            *reinterpret_cast<bf16x4*>(arow + j0) = yb;
+          } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) arow[lds_col<P>(j0 + b)] = get(y, b);
+          }
+        }
+        if (!EVAL) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const unsigned long long m = __ballot((bits >> b) & 1u);
+            if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+          }
         }
       }
     }
@@ -291,52 +364,62 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
   __syncthreads();
 
   // ---- phase 2: Z = Y R^T with the objective fused into the epilogue
-  // Accumulators c{m}{n}: 32x32 block (row block m, column block nb0 + n).
-  // Named values, not arrays, so that every index is static.
+  // Accumulators c{m}{n}: 32x32 block (row block m, column block nb0 + n),
+  // named values rather than arrays so that every index is static.
   const int nblk = dpad / 32;
   floatx16 part0 = {}, part1 = {};
-  for (int nb0 = wave * kNB; nb0 < nblk; nb0 += kRotWaves * kNB) {
+  for (int nb0 = wave * 2; nb0 < nblk; nb0 += kRotWaves * 2) {
     floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
     if constexpr (sizeof(T) == 2) {
-      // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per block
+      // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per
+      // block and K-step; dpad / 16 is a multiple of 4.
       const bf16x8* rop = reinterpret_cast<const bf16x8*>(a.rop);
       const int kbn = dpad / 16;
       const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
       const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
       const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
-      for (int kb = 0; kb < kbn; ++kb) {
-        const bf16x8 b0 = rb0[(size_t)kb * 64];
-        const bf16x8 b1 = rb1[(size_t)kb * 64];
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ar + kb * 16);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, c01, 0, 0, 0);
-        if constexpr (MB == 2) {
-          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(
-              ar + (size_t)32 * stride + kb * 16);
-          c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, c10, 0, 0, 0);
-          c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, c11, 0, 0, 0);
+      bf16x8 p00 = rb0[0], p01 = rb0[64], p02 = rb0[128], p03 = rb0[192];
+      bf16x8 p10 = rb1[0], p11 = rb1[64], p12 = rb1[128], p13 = rb1[192];
+      for (int kb = 0; kb < kbn; kb += 4) {
+        const bf16x8 q00 = p00, q01 = p01, q02 = p02, q03 = p03;
+        const bf16x8 q10 = p10, q11 = p11, q12 = p12, q13 = p13;
+        if (kb + 4 < kbn) {
+          const size_t nx = (size_t)(kb + 4) * 64;
+          p00 = rb0[nx];
+          p01 = rb0[nx + 64];
+          p02 = rb0[nx + 128];
+          p03 = rb0[nx + 192];
+          p10 = rb1[nx];
+          p11 = rb1[nx + 64];
+          p12 = rb1[nx + 128];
+          p13 = rb1[nx + 192];
         }
+        bf16_step<MB>(ar, stride, kb + 0, q00, q10, c00, c01, c10, c11);
+        bf16_step<MB>(ar, stride, kb + 1, q01, q11, c00, c01, c10, c11);
+        bf16_step<MB>(ar, stride, kb + 2, q02, q12, c00, c01, c10, c11);
+        bf16_step<MB>(ar, stride, kb + 3, q03, q13, c00, c01, c10, c11);
       }
     } else {
-      // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps
+      // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps;
+      // dpad / 8 is a multiple of 2.
       const float4* rop = reinterpret_cast<const float4*>(a.rop);
       const int k8n = dpad / 8;
       const float4* rb0 = rop + ((size_t)nb0 * k8n) * 64 + lane;
       const float4* rb1 = rb0 + (size_t)k8n * 64;
       const float* ar = reinterpret_cast<const float*>(At) +
                         (size_t)(lane % 32) * stride + 4 * (lane / 32);
-      for (int k8 = 0; k8 < k8n; ++k8) {
-        const float4 b0 = rb0[(size_t)k8 * 64];
-        const float4 b1 = rb1[(size_t)k8 * 64];
-        const float4 av = *reinterpret_cast<const float4*>(ar + k8 * 8);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b0.x, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b1.x, c01, 0, 0, 0);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b0.y, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b1.y, c01, 0, 0, 0);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b0.z, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b1.z, c01, 0, 0, 0);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b0.w, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b1.w, c01, 0, 0, 0);
+      float4 p00 = rb0[0], p01 = rb0[64], p10 = rb1[0], p11 = rb1[64];
+      for (int k8 = 0; k8 < k8n; k8 += 2) {
+        const float4 q00 = p00, q01 = p01, q10 = p10, q11 = p11;
+        if (k8 + 2 < k8n) {
+          const size_t nx = (size_t)(k8 + 2) * 64;
+          p00 = rb0[nx];
+          p01 = rb0[nx + 64];
+          p10 = rb1[nx];
+          p11 = rb1[nx + 64];
+        }
+        f32_step(ar, k8 + 0, q00, q10, c00, c01);
+        f32_step(ar, k8 + 1, q01, q11, c00, c01);
       }
     }
     osc_accumulate(part0, c00);
@@ -373,29 +456,49 @@ __global__ __launch_bounds__(kRotThreads) void k_rot(GenArgs a) {
     const size_t g = (size_t)run * a.NP + i;
     const float fx = a.fit_cur[g];
     const bool accept = f < fx;
-    const float* xrow = base + (size_t)i * a.ldx;
-    float* nrow = a.pop_next + g * a.ldx;
-    const float* x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
-    const float* x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
-    const float* x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
-    for (int t = 0; t < tq; ++t) {
-      const int q = lane + 64 * t, j0 = 4 * q;
-      if (j0 >= a.D) continue;
-      float4 xv = ld4(xrow + j0);
-      if (accept) {
-        const float4 v1 = ld4(x1 + j0), v2 = ld4(x2 + j0), v3 = ld4(x3 + j0);
+    const bool refresh = !accept && a.changed[g] != 0;
+    if (accept || refresh) {
+      const float* xrow = base + (size_t)i * a.ldx;
+      float* nrow = a.pop_next + g * a.ldx;
+      const float* x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
+      const float* x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
+      const float* x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+      for (int t0 = 0; t0 < tq; t0 += 4) {
+        float4 xv[4], v1[4], v2[4], v3[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const unsigned long long m = planes[((size_t)rl * tq + t) * 4 + b];
-          if ((m >> lane) & 1ull)
-            set(xv, b, mutant_coord(get(v1, b), get(v2, b), get(v3, b), a.F,
-                                    a.lo, a.hi));
+        for (int u = 0; u < 4; ++u) {
+          const int j0 = 4 * (lane + 64 * (t0 + u));
+          if (t0 + u < tq && j0 < a.D) {
+            xv[u] = ld4(xrow + j0);
+            if (accept) {
+              v1[u] = ld4(x1 + j0);
+              v2[u] = ld4(x2 + j0);
+              v3[u] = ld4(x3 + j0);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + u;
+          const int j0 = 4 * (lane + 64 * t);
+          if (t >= tq || j0 >= a.D) continue;
+          float4 out = xv[u];
+          if (accept) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const unsigned long long m = planes[((size_t)rl * tq + t) * 4 + b];
+              if ((m >> lane) & 1ull)
+                set(out, b, mutant_coord(get(v1[u], b), get(v2[u], b),
+                                         get(v3[u], b), a.F, a.lo, a.hi));
+            }
+          }
+          st4(nrow + j0, out);
         }
       }
-      st4(nrow + j0, xv);
     }
     if (lane == 0) {
       a.fit_next[g] = accept ? f : fx;
+      a.changed[g] = accept ? 1 : 0;
       if (accept) record_accept(a, run, i, f);
     }
   }
@@ -478,6 +581,13 @@ __global__ void k_stats_reset(GenArgs a, int reset_accepted) {
     if (reset_accepted) a.accepted[r] = 0ull;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.done = 0u;
+}
+
+// Every row of the other buffer is stale (after initialisation or a load).
+__global__ __launch_bounds__(256) void k_mark_changed(unsigned char* changed,
+                                                      int n) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < n; t += gridDim.x * 256)
+    changed[t] = 1;
 }
 
 // best_key[r] = min over i of key(fit[r][i], i); one wave per run slice.
@@ -582,33 +692,59 @@ hipError_t launch_sep_e(const GenArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-template <class P, bool EVAL>
+template <class P, int BM, int NT, bool EVAL>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
-  const size_t lds = rot_lds_bytes<P>(a.dpad);
+  const size_t lds = rot_lds_bytes<P, BM, NT>(a.dpad);
   static bool attr_done = false;
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_rot<P, EVAL>),
+        reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
     if (e != hipSuccess) return e;
     attr_done = true;
   }
   int blocks;
   if (EVAL) {
-    blocks = (a.nrows + P::BM - 1) / P::BM;
+    blocks = (a.nrows + BM - 1) / BM;
   } else {
-    blocks = a.runs * ((a.NP + P::BM - 1) / P::BM);
+    blocks = a.runs * ((a.NP + BM - 1) / BM);
   }
-  hipLaunchKernelGGL((k_rot<P, EVAL>), dim3(blocks), dim3(kRotThreads), lds, s,
+  hipLaunchKernelGGL((k_rot<P, BM, NT, EVAL>), dim3(blocks), dim3(NT), lds, s,
                      a);
   return hipGetLastError();
 }
 
+template <bool EVAL>
+hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
+  if (prec != kPrecBF16) return launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
+  if (rot_tile_rows(prec, a.dpad) == 64)
+    return launch_rot_t<PrecBF16, 64, 512, EVAL>(a, s);
+  return launch_rot_t<PrecBF16, 32, 256, EVAL>(a, s);
+}
+
 }  // namespace
 
+// Rows per rotated tile.  BF16 defaults to 64 rows and 512 threads (R, the
+// B operand streamed from L2, is reused by 64 rows); DE_ROT_TILE_ROWS=32
+// selects 32-row tiles of 256 threads, two workgroups per CU, whose memory
+// and MFMA phases can overlap.
+int rot_tile_rows(int prec, int dpad) {
+  if (prec != kPrecBF16) return 32;
+  static int forced = -1;
+  if (forced < 0) {
+    const char* e = getenv("DE_ROT_TILE_ROWS");
+    forced = (e && atoi(e) == 32) ? 32 : 0;
+  }
+  if (forced == 32) return 32;
+  return rot_lds_bytes<PrecBF16, 64, 512>(dpad) <= (size_t)kMaxLdsBytes ? 64
+                                                                        : 32;
+}
+
 size_t rot_lds_bytes_host(int prec, int dpad) {
-  return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16>(dpad)
-                           : rot_lds_bytes<PrecF32>(dpad);
+  if (prec != kPrecBF16) return rot_lds_bytes<PrecF32, 32, 512>(dpad);
+  return rot_tile_rows(prec, dpad) == 64
+             ? rot_lds_bytes<PrecBF16, 64, 512>(dpad)
+             : rot_lds_bytes<PrecBF16, 32, 256>(dpad);
 }
 
 bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
@@ -616,14 +752,12 @@ bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,
                              hipStream_t s) {
   if (kind == kObjSphere) return launch_sep_e<false>(a, s);
-  return prec == kPrecBF16 ? launch_rot_t<PrecBF16, false>(a, s)
-                           : launch_rot_t<PrecF32, false>(a, s);
+  return launch_rot_e<false>(a, prec, s);
 }
 
 hipError_t launch_eval(const GenArgs& a, int kind, int prec, hipStream_t s) {
   if (kind == kObjSphere) return launch_sep_e<true>(a, s);
-  return prec == kPrecBF16 ? launch_rot_t<PrecBF16, true>(a, s)
-                           : launch_rot_t<PrecF32, true>(a, s);
+  return launch_rot_e<true>(a, prec, s);
 }
 
 hipError_t launch_init(const GenArgs& a, hipStream_t s) {
@@ -654,6 +788,13 @@ hipError_t launch_stats_reset(const GenArgs& a, bool reset_accepted,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_stats_reset, dim3(grid_for(a.runs, 256)), dim3(256), 0,
                      s, a, reset_accepted ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_changed(const GenArgs& a, hipStream_t s) {
+  const int n = a.runs * a.NP;
+  hipLaunchKernelGGL(k_mark_changed, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                     a.changed, n);
   return hipGetLastError();
 }
 
