@@ -110,6 +110,27 @@ def time_workload(name, steps, warmup, seed=1):
                 best_median=float(sorted(best)[len(best) // 2]))
 
 
+def copy_ceiling(nbytes=1 << 30, reps=20):
+    """Device-to-device copy of nbytes (read + write), timed with events:
+    the measured HBM ceiling next to the 8 TB/s specification."""
+    import torch
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return dict(bytes_moved=2 * nbytes, ms=round(ms, 4),
+                GBps=round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
+
+
 def time_to_target(target=1e-8, max_gens=5000, check_every=50):
     import torch
 
@@ -172,6 +193,8 @@ def main():
                     choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy first (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the DE step is single-GPU in "
@@ -182,6 +205,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.copy_calibration:
+        copy_ceiling(nbytes=256 << 20, reps=1)
     main_res = time_workload(args.workload, args.steps, args.warmup)
     w = WORKLOADS[args.workload]
     line = {
@@ -215,6 +240,7 @@ def main():
             "kernel_ms_per_step": round(c["kernel_ms"], 5),
             "roofline": c["roofline"]}
         line["time_to_target"] = time_to_target()
+        line["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line), flush=True)

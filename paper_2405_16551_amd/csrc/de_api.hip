@@ -30,7 +30,9 @@ struct Layout {
 
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
-int dpad_for(int D) { return (int)round_up((size_t)D, 64); }
+// D padded for the MFMA tiling: 128 keeps the BF16 K loop a multiple of
+// eight K-steps of 16.
+int dpad_for(int D) { return (int)round_up((size_t)D, 128); }
 
 Layout layout_for(const de_params& p, int kind, int prec) {
   Layout L{};

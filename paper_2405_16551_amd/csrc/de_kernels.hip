@@ -57,33 +57,6 @@ __device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
   }
 }
 
-// Trial coordinates j0..j0+3 of one individual (eqs. 2, 3); coordinates at
-// or beyond D keep the target's value.
-__device__ __forceinline__ float4 trial4(const GenArgs& a, uint32_t run,
-                                         int i, int q, const Donors& d,
-                                         const float* x1, const float* x2,
-                                         const float* x3, float4 xv,
-                                         uint32_t* take_bits) {
-  const int j0 = 4 * q;
-  const Words4 w = draw_block(kTagXover, run, a.gen, (uint32_t)i, (uint32_t)q,
-                              a.key_lo, a.key_hi);
-  const float4 v1 = ld4(x1 + j0), v2 = ld4(x2 + j0), v3 = ld4(x3 + j0);
-  float4 u = xv;
-  uint32_t bits = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const bool t = (j0 + b < a.D) && take_mutant(w.w[b], j0 + b, d.jrand,
-                                                 a.cr_threshold);
-    if (t) {
-      set(u, b, mutant_coord(get(v1, b), get(v2, b), get(v3, b), a.F, a.lo,
-                             a.hi));
-      bits |= 1u << b;
-    }
-  }
-  if (take_bits) *take_bits = bits;
-  return u;
-}
-
 // ---------------------------------------------------------------------------
 // Separable objective.  EVAL: f of rows pop_cur[0..nrows) into fit_next.
 template <int LPI, int ITER, bool EVAL>
@@ -96,6 +69,10 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
   const int run = EVAL ? 0 : g / a.NP;
   const int i = EVAL ? g : g - run * a.NP;
   const float* xrow = a.pop_cur + (size_t)g * a.ldx;
+  // Last 4-coordinate chunk that lies inside every row: loads past the end
+  // of a row are redirected there (and their values ignored), so no load
+  // sits behind a per-lane branch and all of them stay in flight together.
+  const int dlast = ((a.D + 3) / 4 - 1) * 4;
 
   Donors d{0, 0, 0, 0};
   const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
@@ -106,24 +83,40 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
     x2 = base + (size_t)d.r2 * a.ldx;
     x3 = base + (size_t)d.r3 * a.ldx;
   }
-  float4 xv[ITER], uv[ITER];
+  float4 xv[ITER], uv[ITER], v1[ITER], v2[ITER], v3[ITER], ov[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int jl = min(4 * (ln + it * LPI), dlast);
+    xv[it] = ld4(xrow + jl);
+    ov[it] = ld4(a.o + jl);
+    if (!EVAL) {
+      v1[it] = ld4(x1 + jl);
+      v2[it] = ld4(x2 + jl);
+      v3[it] = ld4(x3 + jl);
+    }
+  }
   float acc = 0.f;
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int q = ln + it * LPI, j0 = 4 * q;
-    if (j0 < a.D) {
-      xv[it] = ld4(xrow + j0);
-      uv[it] = EVAL ? xv[it]
-                    : trial4(a, (uint32_t)run, i, q, d, x1, x2, x3, xv[it],
-                             nullptr);
-      const float4 ov = ld4(a.o + j0);
+    uv[it] = xv[it];
+    if (!EVAL) {
+      const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen,
+                                  (uint32_t)i, (uint32_t)q, a.key_lo,
+                                  a.key_hi);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if (j0 + b < a.D) {
-          const float y = get(uv[it], b) - get(ov, b);
-          acc = fmaf(y, y, acc);
-        }
+        const bool tk = (j0 + b < a.D) &&
+                        take_mutant(w.w[b], j0 + b, d.jrand, a.cr_threshold);
+        const float mv = mutant_coord(get(v1[it], b), get(v2[it], b),
+                                      get(v3[it], b), a.F, a.lo, a.hi);
+        set(uv[it], b, tk ? mv : get(xv[it], b));
       }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float y = get(uv[it], b) - get(ov[it], b);
+      acc = (j0 + b < a.D) ? fmaf(y, y, acc) : acc;
     }
   }
   const float f = group_sum<LPI>(acc);
@@ -204,21 +197,51 @@ __device__ __forceinline__ void osc_accumulate(floatx16& part,
   for (int r = 0; r < 16; ++r) part[r] += osc_term(c[r]);
 }
 
-// One BF16 K-step (16) of the wave tile: rows 0-31 (and 32-63), columns of
-// two 32-wide blocks.
+// Target and donor chunks of one row, for a group of four 256-coordinate
+// chunks.
+struct RowChunks {
+  float4 xv[4], v1[4], v2[4], v3[4];
+};
+
+// R fragments of four consecutive K-steps for two column blocks.
+struct BFrags {
+  bf16x8 b0[4], b1[4];
+};
+
+__device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
+                                            const bf16x8* rb1, int kb) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    f.b0[u] = rb0[(size_t)(kb + u) * 64];
+    f.b1[u] = rb1[(size_t)(kb + u) * 64];
+  }
+}
+
+// Four BF16 K-steps of the wave tile: the A fragments of the group are read
+// from LDS first, then the MFMAs run.
 template <int MB>
-__device__ __forceinline__ void bf16_step(const __bf16* ar, int stride, int kb,
-                                          bf16x8 b0, bf16x8 b1, floatx16& c00,
-                                          floatx16& c01, floatx16& c10,
-                                          floatx16& c11) {
-  const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(ar + kb * 16);
-  c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, c00, 0, 0, 0);
-  c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, c01, 0, 0, 0);
-  if constexpr (MB == 2) {
-    const bf16x8 a1 =
-        *reinterpret_cast<const bf16x8*>(ar + (size_t)32 * stride + kb * 16);
-    c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, c10, 0, 0, 0);
-    c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, c11, 0, 0, 0);
+__device__ __forceinline__ void bf16_group(const __bf16* ar, int stride,
+                                           int kb, const BFrags& f,
+                                           floatx16& c00, floatx16& c01,
+                                           floatx16& c10, floatx16& c11) {
+  bf16x8 a0[4], a1[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    a0[u] = *reinterpret_cast<const bf16x8*>(ar + (kb + u) * 16);
+    if constexpr (MB == 2)
+      a1[u] = *reinterpret_cast<const bf16x8*>(ar + (size_t)32 * stride +
+                                               (kb + u) * 16);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], f.b0[u], c00, 0, 0, 0);
+    c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], f.b1[u], c01, 0, 0, 0);
+    if constexpr (MB == 2) {
+      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], f.b0[u], c10, 0, 0,
+                                                    0);
+      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], f.b1[u], c11, 0, 0,
+                                                    0);
+    }
   }
 }
 
@@ -280,82 +303,108 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
     }
     __syncthreads();
   }
-  for (int rl = wave; rl < BM; rl += kRotWaves) {
+  // Rows rl = wave + kRotWaves * k of this wave; each row is cut into groups
+  // of four 256-coordinate chunks.  Items (row, group) are processed in
+  // order with two register sets, so the loads of item s + 1 are in flight
+  // while item s is drawn, mutated and stored.
+  for (int rl = nvalid + (((wave - nvalid) % kRotWaves) + kRotWaves) %
+                             kRotWaves;
+       rl < BM; rl += kRotWaves) {
     T* arow = At + (size_t)rl * stride;
-    if (rl >= nvalid) {
-      for (int k = lane; k < dpad; k += 64) arow[k] = (T)0.0f;
-      continue;
-    }
-    const int i = row0 + rl;
-    const float* xrow = base + (size_t)i * a.ldx;
-    const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
-    int jrand = 0;
-    if (!EVAL) {
-      x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
-      x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
-      x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
-      jrand = donors[rl * 4 + 3];
-    }
+    for (int k = lane; k < dpad; k += 64) arow[k] = (T)0.0f;
+  }
+  {
+    // Rows rl = wave + kRotWaves * k of this wave, two rows per step: the
+    // target and donor chunks of both rows (groups of four 256-coordinate
+    // chunks) are requested together, then drawn, mutated and stored.
+    // Loads past the end of a row go to its last chunk (values unused), so
+    // no load sits behind a per-lane branch.
+    const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
+    const int dlast = ((a.D + 3) / 4 - 1) * 4;
     for (int t0 = 0; t0 < tq; t0 += 4) {
-      float4 xv[4], v1[4], v2[4], v3[4];
+      float4 ov[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j0 = 4 * (lane + 64 * (t0 + u));
-        if (t0 + u < tq && j0 < a.D) {
-          xv[u] = ld4(xrow + j0);
+      for (int u = 0; u < 4; ++u)
+        ov[u] = ld4(a.o + min(4 * (lane + 64 * (t0 + u)), dlast));
+      for (int k = 0; k < nrow_w; k += 2) {
+        const bool two = k + 1 < nrow_w;
+        RowChunks c[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rl = wave + kRotWaves * (two ? k + h : k);
+          const float* xrow = base + (size_t)(row0 + rl) * a.ldx;
+          const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
           if (!EVAL) {
-            v1[u] = ld4(x1 + j0);
-            v2[u] = ld4(x2 + j0);
-            v3[u] = ld4(x3 + j0);
+            x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
+            x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
+            x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
           }
-        }
-      }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int t = t0 + u;
-        if (t >= tq) break;
-        const int q = lane + 64 * t, j0 = 4 * q;
-        uint32_t bits = 0;
-        float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j0 < a.D) {
-          float4 uu = xv[u];
-          if (!EVAL) {
-            const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen,
-                                        (uint32_t)i, (uint32_t)q, a.key_lo,
-                                        a.key_hi);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              if (j0 + b < a.D &&
-                  take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold)) {
-                set(uu, b, mutant_coord(get(v1[u], b), get(v2[u], b),
-                                        get(v3[u], b), a.F, a.lo, a.hi));
-                bits |= 1u << b;
-              }
+          for (int u = 0; u < 4; ++u) {
+            const int jl = min(4 * (lane + 64 * (t0 + u)), dlast);
+            c[h].xv[u] = ld4(xrow + jl);
+            if (!EVAL) {
+              c[h].v1[u] = ld4(x1 + jl);
+              c[h].v2[u] = ld4(x2 + jl);
+              c[h].v3[u] = ld4(x3 + jl);
             }
           }
-          const float4 ov = ld4(a.o + j0);
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            set(y, b, (j0 + b < a.D) ? get(uu, b) - get(ov, b) : 0.f);
         }
-        if (j0 < dpad) {
-          if constexpr (sizeof(T) == 2) {
-            bf16x4 yb;
-            yb[0] = (__bf16)y.x;
-            yb[1] = (__bf16)y.y;
-            yb[2] = (__bf16)y.z;
-            yb[3] = (__bf16)y.w;
-            *reinterpret_cast<bf16x4*>(arow + j0) = yb;
-          } else {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) arow[lds_col<P>(j0 + b)] = get(y, b);
-          }
-        }
-        if (!EVAL) {
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && !two) break;
+          const int rl = wave + kRotWaves * (k + h);
+          const int i = row0 + rl;
+          const int jrand = EVAL ? 0 : donors[rl * 4 + 3];
+          T* arow = At + (size_t)rl * stride;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const unsigned long long m = __ballot((bits >> b) & 1u);
-            if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            if (t >= tq) break;
+            const int q = lane + 64 * t, j0 = 4 * q;
+            uint32_t bits = 0;
+            float4 uu = c[h].xv[u];
+            if (!EVAL) {
+              const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen,
+                                          (uint32_t)i, (uint32_t)q, a.key_lo,
+                                          a.key_hi);
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const bool tk =
+                    (j0 + b < a.D) &&
+                    take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold);
+                const float mv =
+                    mutant_coord(get(c[h].v1[u], b), get(c[h].v2[u], b),
+                                 get(c[h].v3[u], b), a.F, a.lo, a.hi);
+                set(uu, b, tk ? mv : get(c[h].xv[u], b));
+                bits |= (tk ? 1u : 0u) << b;
+              }
+            }
+            float4 y;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              set(y, b, (j0 + b < a.D) ? get(uu, b) - get(ov[u], b) : 0.f);
+            if (j0 < dpad) {
+              if constexpr (sizeof(T) == 2) {
+                bf16x4 yb;
+                yb[0] = (__bf16)y.x;
+                yb[1] = (__bf16)y.y;
+                yb[2] = (__bf16)y.z;
+                yb[3] = (__bf16)y.w;
+                *reinterpret_cast<bf16x4*>(arow + j0) = yb;
+              } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                  arow[lds_col<P>(j0 + b)] = get(y, b);
+              }
+            }
+            if (!EVAL) {
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const unsigned long long m = __ballot((bits >> b) & 1u);
+                if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+              }
+            }
           }
         }
       }
@@ -378,26 +427,16 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
       const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
       const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
       const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
-      bf16x8 p00 = rb0[0], p01 = rb0[64], p02 = rb0[128], p03 = rb0[192];
-      bf16x8 p10 = rb1[0], p11 = rb1[64], p12 = rb1[128], p13 = rb1[192];
-      for (int kb = 0; kb < kbn; kb += 4) {
-        const bf16x8 q00 = p00, q01 = p01, q02 = p02, q03 = p03;
-        const bf16x8 q10 = p10, q11 = p11, q12 = p12, q13 = p13;
-        if (kb + 4 < kbn) {
-          const size_t nx = (size_t)(kb + 4) * 64;
-          p00 = rb0[nx];
-          p01 = rb0[nx + 64];
-          p02 = rb0[nx + 128];
-          p03 = rb0[nx + 192];
-          p10 = rb1[nx];
-          p11 = rb1[nx + 64];
-          p12 = rb1[nx + 128];
-          p13 = rb1[nx + 192];
-        }
-        bf16_step<MB>(ar, stride, kb + 0, q00, q10, c00, c01, c10, c11);
-        bf16_step<MB>(ar, stride, kb + 1, q01, q11, c00, c01, c10, c11);
-        bf16_step<MB>(ar, stride, kb + 2, q02, q12, c00, c01, c10, c11);
-        bf16_step<MB>(ar, stride, kb + 3, q03, q13, c00, c01, c10, c11);
+      // Two register sets of R fragments (four K-steps, two column blocks)
+      // alternate, so each group's loads are in flight during the previous
+      // group's MFMAs; dpad / 16 is a multiple of 8.
+      BFrags fa, fb;
+      load_bfrags(fa, rb0, rb1, 0);
+      for (int kb = 0; kb < kbn; kb += 8) {
+        load_bfrags(fb, rb0, rb1, kb + 4);
+        bf16_group<MB>(ar, stride, kb, fa, c00, c01, c10, c11);
+        if (kb + 8 < kbn) load_bfrags(fa, rb0, rb1, kb + 8);
+        bf16_group<MB>(ar, stride, kb + 4, fb, c00, c01, c10, c11);
       }
     } else {
       // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps;
@@ -463,36 +502,35 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
       const float* x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
       const float* x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
       const float* x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+      const int dlast = ((a.D + 3) / 4 - 1) * 4;
       for (int t0 = 0; t0 < tq; t0 += 4) {
         float4 xv[4], v1[4], v2[4], v3[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int j0 = 4 * (lane + 64 * (t0 + u));
-          if (t0 + u < tq && j0 < a.D) {
-            xv[u] = ld4(xrow + j0);
-            if (accept) {
-              v1[u] = ld4(x1 + j0);
-              v2[u] = ld4(x2 + j0);
-              v3[u] = ld4(x3 + j0);
-            }
+          const int jl = min(4 * (lane + 64 * (t0 + u)), dlast);
+          xv[u] = ld4(xrow + jl);
+          if (accept) {
+            v1[u] = ld4(x1 + jl);
+            v2[u] = ld4(x2 + jl);
+            v3[u] = ld4(x3 + jl);
           }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int t = t0 + u;
+          if (t >= tq) break;
           const int j0 = 4 * (lane + 64 * t);
-          if (t >= tq || j0 >= a.D) continue;
           float4 out = xv[u];
           if (accept) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
               const unsigned long long m = planes[((size_t)rl * tq + t) * 4 + b];
-              if ((m >> lane) & 1ull)
-                set(out, b, mutant_coord(get(v1[u], b), get(v2[u], b),
-                                         get(v3[u], b), a.F, a.lo, a.hi));
+              const float mv = mutant_coord(get(v1[u], b), get(v2[u], b),
+                                            get(v3[u], b), a.F, a.lo, a.hi);
+              set(out, b, ((m >> lane) & 1ull) ? mv : get(xv[u], b));
             }
           }
-          st4(nrow + j0, out);
+          if (j0 < a.D) st4(nrow + j0, out);
         }
       }
     }
