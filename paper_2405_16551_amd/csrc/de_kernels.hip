@@ -217,30 +217,39 @@ __device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
   }
 }
 
-// Four BF16 K-steps of the wave tile: the A fragments of the group are read
-// from LDS first, then the MFMAs run.
+// A fragments (rows 0-31 and 32-63) of four consecutive K-steps.
+struct AFrags {
+  bf16x8 a0[4], a1[4];
+};
+
 template <int MB>
-__device__ __forceinline__ void bf16_group(const __bf16* ar, int stride,
-                                           int kb, const BFrags& f,
+__device__ __forceinline__ void load_afrags(AFrags& f, const __bf16* ar,
+                                            int stride, int kb) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    f.a0[u] = *reinterpret_cast<const bf16x8*>(ar + (kb + u) * 16);
+    if constexpr (MB == 2)
+      f.a1[u] = *reinterpret_cast<const bf16x8*>(ar + (size_t)32 * stride +
+                                                 (kb + u) * 16);
+  }
+}
+
+// MFMAs of four BF16 K-steps of the wave tile.
+template <int MB>
+__device__ __forceinline__ void bf16_group(const AFrags& fa, const BFrags& f,
                                            floatx16& c00, floatx16& c01,
                                            floatx16& c10, floatx16& c11) {
-  bf16x8 a0[4], a1[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    a0[u] = *reinterpret_cast<const bf16x8*>(ar + (kb + u) * 16);
-    if constexpr (MB == 2)
-      a1[u] = *reinterpret_cast<const bf16x8*>(ar + (size_t)32 * stride +
-                                               (kb + u) * 16);
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], f.b0[u], c00, 0, 0, 0);
-    c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], f.b1[u], c01, 0, 0, 0);
+    c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a0[u], f.b0[u], c00, 0, 0,
+                                                  0);
+    c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a0[u], f.b1[u], c01, 0, 0,
+                                                  0);
     if constexpr (MB == 2) {
-      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], f.b0[u], c10, 0, 0,
-                                                    0);
-      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], f.b1[u], c11, 0, 0,
-                                                    0);
+      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a1[u], f.b0[u], c10, 0,
+                                                    0, 0);
+      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a1[u], f.b1[u], c11, 0,
+                                                    0, 0);
     }
   }
 }
@@ -415,6 +424,8 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
   // ---- phase 2: Z = Y R^T with the objective fused into the epilogue
   // Accumulators c{m}{n}: 32x32 block (row block m, column block nb0 + n),
   // named values rather than arrays so that every index is static.
+  // Wave w of every workgroup streams the same R fragments at about the same
+  // time, so concurrent requests from the CUs of an XCD share L2 lines.
   const int nblk = dpad / 32;
   floatx16 part0 = {}, part1 = {};
   for (int nb0 = wave * 2; nb0 < nblk; nb0 += kRotWaves * 2) {
@@ -427,16 +438,28 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
       const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
       const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
       const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
-      // Two register sets of R fragments (four K-steps, two column blocks)
-      // alternate, so each group's loads are in flight during the previous
-      // group's MFMAs; dpad / 16 is a multiple of 8.
+      // Two register sets of A fragments (LDS) and R fragments (L2), four
+      // K-steps each, alternate: the next group's reads are issued before
+      // the current group's MFMAs, and scheduling barriers keep them there.
+      // dpad / 16 is a multiple of 8.
+      auto kphys = [](int kb) { return kb; };
+      AFrags aa, ab;
       BFrags fa, fb;
-      load_bfrags(fa, rb0, rb1, 0);
+      load_afrags<MB>(aa, ar, stride, kphys(0));
+      load_bfrags(fa, rb0, rb1, kphys(0));
       for (int kb = 0; kb < kbn; kb += 8) {
-        load_bfrags(fb, rb0, rb1, kb + 4);
-        bf16_group<MB>(ar, stride, kb, fa, c00, c01, c10, c11);
-        if (kb + 8 < kbn) load_bfrags(fa, rb0, rb1, kb + 8);
-        bf16_group<MB>(ar, stride, kb + 4, fb, c00, c01, c10, c11);
+        load_afrags<MB>(ab, ar, stride, kphys(kb + 4));
+        load_bfrags(fb, rb0, rb1, kphys(kb + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        bf16_group<MB>(aa, fa, c00, c01, c10, c11);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + 8 < kbn) {
+          load_afrags<MB>(aa, ar, stride, kphys(kb + 8));
+          load_bfrags(fa, rb0, rb1, kphys(kb + 8));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        bf16_group<MB>(ab, fb, c00, c01, c10, c11);
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps;
@@ -469,16 +492,30 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
     }
   }
   // 32x32 accumulator layout: register r of lane l holds row
-  // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.
+  // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.  Each lane
+  // has 32 per-row partial sums (value v = 16 m + r); a reduce-scatter
+  // butterfly over the 32 lanes of each half-wave leaves lane l with the
+  // total of value v = l % 32 (31 exchanges instead of 5 per value).
+  {
+    float v[32];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-    const float s0 = group_sum<32>(part0[r]);
-    if ((lane % 32) == 0) fpart[wave * BM + row] = s0;
-    if constexpr (MB == 2) {
-      const float s1 = group_sum<32>(part1[r]);
-      if ((lane % 32) == 0) fpart[wave * BM + 32 + row] = s1;
+    for (int r = 0; r < 16; ++r) {
+      v[r] = part0[r];
+      v[16 + r] = MB == 2 ? part1[r] : 0.f;
     }
+#pragma unroll
+    for (int m = 16, n = 32; m >= 1; m >>= 1, n >>= 1) {
+      const bool upper = (lane & m) != 0;
+#pragma unroll
+      for (int k = 0; k < n / 2; ++k) {
+        const float send = upper ? v[k] : v[k + n / 2];
+        const float keep = upper ? v[k + n / 2] : v[k];
+        v[k] = keep + __shfl_xor(send, m, 64);
+      }
+    }
+    const int idx = lane % 32, mb = idx / 16, r = idx % 16;
+    const int row = mb * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+    if (mb < MB) fpart[wave * BM + row] = v[0];
   }
   __syncthreads();
 
