@@ -18,6 +18,7 @@ CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -54,14 +55,42 @@ def describe(name):
             f"{obj}, F=0.5, CR=0.9")
 
 
-def algorithmic(w, trials):
-    """Algorithmic work of one generation launch: FLOPs of the rotation
-    product (2 D^2 per trial) or HBM bytes of the separable step (read the
-    target row, write the next row: 8 D + 8 bytes per trial)."""
+def algorithmic(w, trials, accept_rate):
+    """Algorithmic work of one generation launch.  Rotated objective: FLOPs
+    of the rotation product, 2 D^2 per trial.  Separable objective: HBM bytes
+    every implementation of the step must move, per trial 4 D (read the
+    target row) + 8 (read and write its fitness) + 4 D times the acceptance
+    rate (write the replacing trial vector); donor rows are on-chip reuse."""
     D = w["D"]
     if w["kind"] == "rot_osc":
         return 2.0 * D * D * trials, "TFLOP/s"
-    return (8.0 * D + 8.0) * trials, "GB/s"
+    return (4.0 * D + 8.0 + accept_rate * 4.0 * D) * trials, "GB/s"
+
+
+def kernel_sources_sha256():
+    csrc = os.path.join(ROOT, "paper_2405_16551_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("de_kernels.hip", "de_device.hpp", "de_internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_ms, w):
+    """HBM GB/s of the generation kernel: bytes per launch from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a copy of known
+    size), divided by this run's average launch time.  None when the kernel
+    sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    sha = kernel_sources_sha256()
+    for entry in table.values():
+        if entry.get("workload") == w and entry.get("source_sha256") == sha:
+            return round(entry["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9, 1)
+    return None
 
 
 def time_workload(name, steps, warmup, seed=1):
@@ -78,6 +107,7 @@ def time_workload(name, steps, warmup, seed=1):
     stream = de.stream
     de.generation(warmup)
     torch.cuda.synchronize()
+    acc0, _ = de.stats()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     torch.cuda.synchronize()
@@ -90,7 +120,9 @@ def time_workload(name, steps, warmup, seed=1):
     wall = time.perf_counter() - t0
     kern_ms = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
     trials = w["runs"] * w["NP"]
-    work, unit = algorithmic(w, trials)
+    acc1, best = de.stats()
+    accept_rate = (sum(acc1) - sum(acc0)) / float(trials * steps)
+    work, unit = algorithmic(w, trials, accept_rate)
     if unit == "TFLOP/s":
         achieved = work / (kern_ms * 1e-3) / 1e12
         peak = BF16_PEAK_TFLOPS if w["gemm_prec"] == "bf16" else FP32_PEAK_TFLOPS
@@ -99,14 +131,14 @@ def time_workload(name, steps, warmup, seed=1):
         achieved = work / (kern_ms * 1e-3) / 1e9
         peak = HBM_PEAK_GBS
         bound = "hbm"
-    _, best = de.stats()
     de.close()
     return dict(wall_s=wall, ms_per_step=wall / steps * 1e3,
                 kernel_ms=kern_ms, evals_per_s=trials * steps / wall,
-                gens_per_s=steps / wall,
+                gens_per_s=steps / wall, accept_rate=round(accept_rate, 4),
                 roofline=dict(bound=bound, achieved=round(achieved, 3),
                               peak=peak, unit=unit,
-                              frac=round(achieved / peak, 4), traffic=None),
+                              frac=round(achieved / peak, 4),
+                              traffic=measured_traffic(kern_ms, name)),
                 best_median=float(sorted(best)[len(best) // 2]))
 
 
@@ -230,6 +262,7 @@ def main():
         "gens_per_s": round(main_res["gens_per_s"], 2),
         "kernel_ms_per_step": round(main_res["kernel_ms"], 5),
         "roofline": main_res["roofline"],
+        "accept_rate": main_res["accept_rate"],
     }
     if not args.no_extras:
         comp = "sphere1000" if w["kind"] == "rot_osc" else "rot1000_bf16"
@@ -238,7 +271,7 @@ def main():
             "workload": describe(comp), "evals_per_s": round(c["evals_per_s"], 1),
             "gens_per_s": round(c["gens_per_s"], 2),
             "kernel_ms_per_step": round(c["kernel_ms"], 5),
-            "roofline": c["roofline"]}
+            "accept_rate": c["accept_rate"], "roofline": c["roofline"]}
         line["time_to_target"] = time_to_target()
         line["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
