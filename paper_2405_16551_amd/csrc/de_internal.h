@@ -31,7 +31,6 @@ struct GenArgs {
 };
 
 size_t rot_lds_bytes_host(int prec, int dpad);
-int rot_tile_rows(int prec, int dpad);
 bool sep_supported(int D);
 
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,

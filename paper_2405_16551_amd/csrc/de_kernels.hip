@@ -17,7 +17,6 @@
 //           read from L2 in a fragment-major layout prepared once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include <stdlib.h>
 
 #include "de_device.hpp"
 #include "de_internal.h"
@@ -187,14 +186,28 @@ __device__ __forceinline__ int lds_col(int k) {
 }
 
 // One coordinate of the rotated oscillating objective: z^2 + sin^2(3z).
+// FP32 product: sin^2 from the reduction and series of sin_squared.
+// BF16 product (z already carries BF16 operand rounding, relative error
+// ~2^-8): the hardware sine, which takes its argument in turns; 3z / (2 pi)
+// is reduced to [-1/2, 1/2] turns first (exact), the remaining error is the
+// FP32 rounding of 3z / (2 pi), about 2^-24 |3z| radians.
+template <bool kFastSin>
 __device__ __forceinline__ float osc_term(float z) {
-  return fmaf(z, z, sin_squared(3.0f * z));
+  if constexpr (kFastSin) {
+    constexpr float kTurnsPer3z = 0x1.e8ec8ap-2f;  // 3 / (2 pi)
+    const float turns = z * kTurnsPer3z;
+    const float s = __builtin_amdgcn_sinf(turns - rintf(turns));
+    return fmaf(z, z, s * s);
+  } else {
+    return fmaf(z, z, sin_squared(3.0f * z));
+  }
 }
 
+template <bool kFastSin>
 __device__ __forceinline__ void osc_accumulate(floatx16& part,
                                                const floatx16& c) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) part[r] += osc_term(c[r]);
+  for (int r = 0; r < 16; ++r) part[r] += osc_term<kFastSin>(c[r]);
 }
 
 // Target and donor chunks of one row, for a group of four 256-coordinate
@@ -217,41 +230,22 @@ __device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
   }
 }
 
-// A fragments (rows 0-31 and 32-63) of four consecutive K-steps.
-struct AFrags {
-  bf16x8 a0[4], a1[4];
-};
-
+// Scheduling pattern for one K-step: its LDS reads (next A fragments) and
+// L2 loads (R fragments of a later step) are placed between its MFMAs
+// instead of in one burst, so the matrix unit keeps busy while they go out.
 template <int MB>
-__device__ __forceinline__ void load_afrags(AFrags& f, const __bf16* ar,
-                                            int stride, int kb) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    f.a0[u] = *reinterpret_cast<const bf16x8*>(ar + (kb + u) * 16);
-    if constexpr (MB == 2)
-      f.a1[u] = *reinterpret_cast<const bf16x8*>(ar + (size_t)32 * stride +
-                                                 (kb + u) * 16);
+__device__ __forceinline__ void interleave_step() {
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+  __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+  if constexpr (MB == 2) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
   }
-}
-
-// MFMAs of four BF16 K-steps of the wave tile.
-template <int MB>
-__device__ __forceinline__ void bf16_group(const AFrags& fa, const BFrags& f,
-                                           floatx16& c00, floatx16& c01,
-                                           floatx16& c10, floatx16& c11) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a0[u], f.b0[u], c00, 0, 0,
-                                                  0);
-    c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a0[u], f.b1[u], c01, 0, 0,
-                                                  0);
-    if constexpr (MB == 2) {
-      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a1[u], f.b0[u], c10, 0,
-                                                    0, 0);
-      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa.a1[u], f.b1[u], c11, 0,
-                                                    0, 0);
-    }
-  }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Four FP32 K-steps (8 coordinates) of the wave tile, rows 0-31.
@@ -438,28 +432,49 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
       const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
       const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
       const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
-      // Two register sets of A fragments (LDS) and R fragments (L2), four
-      // K-steps each, alternate: the next group's reads are issued before
-      // the current group's MFMAs, and scheduling barriers keep them there.
-      // dpad / 16 is a multiple of 8.
-      auto kphys = [](int kb) { return kb; };
-      AFrags aa, ab;
+      // Software pipeline at K-step granularity: the A fragments of step
+      // k + 1 are read from LDS while step k's MFMAs run (two slots), and
+      // the R fragments of the next four-step group are loaded from L2 one
+      // pair per step into the other of two register sets.  Each step's
+      // reads are interleaved with its four MFMAs.  dpad / 16 is a multiple
+      // of 8.
+      const T* ar1 = ar + (size_t)32 * stride;
+      bf16x8 a0s[2], a1s[2];
       BFrags fa, fb;
-      load_afrags<MB>(aa, ar, stride, kphys(0));
-      load_bfrags(fa, rb0, rb1, kphys(0));
+      a0s[0] = *reinterpret_cast<const bf16x8*>(ar);
+      if constexpr (MB == 2) a1s[0] = *reinterpret_cast<const bf16x8*>(ar1);
+      load_bfrags(fa, rb0, rb1, 0);
       for (int kb = 0; kb < kbn; kb += 8) {
-        load_afrags<MB>(ab, ar, stride, kphys(kb + 4));
-        load_bfrags(fb, rb0, rb1, kphys(kb + 4));
-        __builtin_amdgcn_sched_barrier(0);
-        bf16_group<MB>(aa, fa, c00, c01, c10, c11);
-        __builtin_amdgcn_sched_barrier(0);
-        if (kb + 8 < kbn) {
-          load_afrags<MB>(aa, ar, stride, kphys(kb + 8));
-          load_bfrags(fa, rb0, rb1, kphys(kb + 8));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = kb + u;
+          const int cur = u & 1, nxt = cur ^ 1;
+          if (u < 7 || k + 1 < kbn) {
+            a0s[nxt] = *reinterpret_cast<const bf16x8*>(ar + (k + 1) * 16);
+            if constexpr (MB == 2)
+              a1s[nxt] = *reinterpret_cast<const bf16x8*>(ar1 + (k + 1) * 16);
+          }
+          if (u < 4) {
+            fb.b0[u] = rb0[(size_t)(kb + 4 + u) * 64];
+            fb.b1[u] = rb1[(size_t)(kb + 4 + u) * 64];
+          } else if (kb + 8 < kbn) {
+            fa.b0[u - 4] = rb0[(size_t)(kb + 8 + u - 4) * 64];
+            fa.b1[u - 4] = rb1[(size_t)(kb + 8 + u - 4) * 64];
+          }
+          const bf16x8 b0 = u < 4 ? fa.b0[u & 3] : fb.b0[u & 3];
+          const bf16x8 b1 = u < 4 ? fa.b1[u & 3] : fb.b1[u & 3];
+          c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b0, c00, 0, 0,
+                                                        0);
+          c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b1, c01, 0, 0,
+                                                        0);
+          if constexpr (MB == 2) {
+            c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b0, c10, 0,
+                                                          0, 0);
+            c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b1, c11, 0,
+                                                          0, 0);
+          }
+          interleave_step<MB>();
         }
-        __builtin_amdgcn_sched_barrier(0);
-        bf16_group<MB>(ab, fb, c00, c01, c10, c11);
-        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps;
@@ -484,11 +499,12 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
         f32_step(ar, k8 + 1, q01, q11, c00, c01);
       }
     }
-    osc_accumulate(part0, c00);
-    osc_accumulate(part0, c01);
+    constexpr bool kFastSin = sizeof(T) == 2;
+    osc_accumulate<kFastSin>(part0, c00);
+    osc_accumulate<kFastSin>(part0, c01);
     if constexpr (MB == 2) {
-      osc_accumulate(part1, c10);
-      osc_accumulate(part1, c11);
+      osc_accumulate<kFastSin>(part1, c10);
+      osc_accumulate<kFastSin>(part1, c11);
     }
   }
   // 32x32 accumulator layout: register r of lane l holds row
@@ -792,34 +808,16 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
 template <bool EVAL>
 hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
   if (prec != kPrecBF16) return launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
-  if (rot_tile_rows(prec, a.dpad) == 64)
-    return launch_rot_t<PrecBF16, 64, 512, EVAL>(a, s);
-  return launch_rot_t<PrecBF16, 32, 256, EVAL>(a, s);
+  return launch_rot_t<PrecBF16, 64, 512, EVAL>(a, s);
 }
 
 }  // namespace
 
-// Rows per rotated tile.  BF16 defaults to 64 rows and 512 threads (R, the
-// B operand streamed from L2, is reused by 64 rows); DE_ROT_TILE_ROWS=32
-// selects 32-row tiles of 256 threads, two workgroups per CU, whose memory
-// and MFMA phases can overlap.
-int rot_tile_rows(int prec, int dpad) {
-  if (prec != kPrecBF16) return 32;
-  static int forced = -1;
-  if (forced < 0) {
-    const char* e = getenv("DE_ROT_TILE_ROWS");
-    forced = (e && atoi(e) == 32) ? 32 : 0;
-  }
-  if (forced == 32) return 32;
-  return rot_lds_bytes<PrecBF16, 64, 512>(dpad) <= (size_t)kMaxLdsBytes ? 64
-                                                                        : 32;
-}
-
+// LDS bytes of the rotated kernel: BF16 tiles of 64 rows, FP32 tiles of 32
+// rows, both 512 threads.
 size_t rot_lds_bytes_host(int prec, int dpad) {
-  if (prec != kPrecBF16) return rot_lds_bytes<PrecF32, 32, 512>(dpad);
-  return rot_tile_rows(prec, dpad) == 64
-             ? rot_lds_bytes<PrecBF16, 64, 512>(dpad)
-             : rot_lds_bytes<PrecBF16, 32, 256>(dpad);
+  return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, 512>(dpad)
+                           : rot_lds_bytes<PrecF32, 32, 512>(dpad);
 }
 
 bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
