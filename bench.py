@@ -122,6 +122,10 @@ def time_workload(name, steps, warmup, seed=1):
     trials = w["runs"] * w["NP"]
     acc1, best = de.stats()
     accept_rate = (sum(acc1) - sum(acc0)) / float(trials * steps)
+    # after the timed region: each run's best as the step computed it
+    # (FP32 / BF16 product) against an FP64 re-evaluation of the same row
+    f64, _ = de.best_f64()
+    rel = [abs(b - e) / e if e > 0 else abs(b) for b, e in zip(best, f64)]
     work, unit = algorithmic(w, trials, accept_rate)
     if unit == "TFLOP/s":
         achieved = work / (kern_ms * 1e-3) / 1e12
@@ -139,7 +143,10 @@ def time_workload(name, steps, warmup, seed=1):
                               peak=peak, unit=unit,
                               frac=round(achieved / peak, 4),
                               traffic=measured_traffic(kern_ms, name)),
-                best_median=float(sorted(best)[len(best) // 2]))
+                best_median=float(sorted(best)[len(best) // 2]),
+                best_vs_fp64=dict(max_rel_err=float(f"{max(rel):.3e}"),
+                                  median_rel_err=float(
+                                      f"{sorted(rel)[len(rel) // 2]:.3e}")))
 
 
 def copy_ceiling(nbytes=1 << 30, reps=20):
@@ -263,6 +270,7 @@ def main():
         "kernel_ms_per_step": round(main_res["kernel_ms"], 5),
         "roofline": main_res["roofline"],
         "accept_rate": main_res["accept_rate"],
+        "best_vs_fp64": main_res["best_vs_fp64"],
     }
     if not args.no_extras:
         comp = "sphere1000" if w["kind"] == "rot_osc" else "rot1000_bf16"

@@ -178,6 +178,17 @@ DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
 DE_API de_status de_best(de_state* state, int32_t run, void* hip_stream,
                   float* x_host, double* f_host, int32_t* idx_host);
 
+/* FP64 re-evaluation of every run's current best individual (the row the
+ * FP32 best key points at): y = x - o and, for DE_OBJ_ROT_OSC, z = R y with R
+ * as the FP32 matrix given at initialisation, are formed in FP64 and f is
+ * summed in FP64 (Section 7.3.1 objective; Section 7.3.4 records the minimum
+ * error).  This states the error of the FP32/BF16 arithmetic of the
+ * generation step against exact arithmetic on the same vector.  f_host
+ * receives runs doubles; idx_host (nullable) runs indices.  Synchronises
+ * hip_stream.                                                              */
+DE_API de_status de_best_f64(de_state* state, void* hip_stream, double* f_host,
+                             int32_t* idx_host);
+
 /* Current generation number of the handle (host-side counter). */
 DE_API de_status de_get_generation(const de_state* state, int64_t* gen);
 

@@ -25,7 +25,7 @@ constexpr uint64_t kMagic = 0x4445'6d69'3335'3578ull;
 constexpr int64_t kGenLimit = int64_t(1) << 32;  // counter field is 32-bit
 
 struct Layout {
-  size_t best, hit, acc, done, changed, opad, rop, total;
+  size_t best, hit, acc, done, changed, opad, rop, rf32, f64, idx, total;
 };
 
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
@@ -50,8 +50,13 @@ Layout layout_for(const de_params& p, int kind, int prec) {
   L.changed = take((size_t)p.runs * p.NP);
   L.opad = take(4 * (size_t)dpad);
   L.rop = 0;
-  if (kind == de::kObjRotOsc)
+  L.rf32 = 0;
+  if (kind == de::kObjRotOsc) {
     L.rop = take((size_t)dpad * dpad * (prec == de::kPrecBF16 ? 2 : 4));
+    L.rf32 = take((size_t)p.D * p.D * 4);
+  }
+  L.f64 = take(8 * (size_t)p.runs);
+  L.idx = take(4 * (size_t)p.runs);
   L.total = off;
   return L;
 }
@@ -299,6 +304,10 @@ DE_API de_status de_init_population(const de_params* params,
                                 p.D, s->dpad, s->kind, s->prec,
                                 reinterpret_cast<float*>(s->work + L.opad),
                                 L.rop ? s->work + L.rop : nullptr, st));
+  if (rc == DE_OK && L.rf32)
+    rc = from_hip(de::launch_copy_rot(objective->R, objective->ldr, p.D,
+                                      reinterpret_cast<float*>(s->work + L.rf32),
+                                      st));
   if (rc == DE_OK) {
     GenArgs a = base_args(s);
     a.pop_next = s->pop[0];
@@ -408,6 +417,35 @@ DE_API de_status de_best(de_state* state, int32_t run, void* hip_stream,
                                  hipMemcpyDeviceToHost, st));
     if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
   }
+  return rc;
+}
+
+DE_API de_status de_best_f64(de_state* state, void* hip_stream,
+                             double* f_host, int32_t* idx_host) {
+  if (!live(state)) return DE_E_STATE;
+  if (!f_host) return DE_E_INVAL;
+  if (state->kind == de::kObjRotOsc && state->p.D > 4096)
+    return DE_E_UNSUPPORTED;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  GenArgs a = base_args(state);
+  a.pop_cur = state->pop[state->gen & 1];
+  double* f64 = reinterpret_cast<double*>(state->work + state->L.f64);
+  int* idx = reinterpret_cast<int*>(state->work + state->L.idx);
+  const float* rf32 = state->L.rf32
+                          ? reinterpret_cast<const float*>(state->work +
+                                                           state->L.rf32)
+                          : nullptr;
+  de_status rc = from_hip(de::launch_best_f64(a, state->kind, rf32, f64, idx,
+                                              st));
+  const int runs = state->p.runs;
+  if (rc == DE_OK)
+    rc = from_hip(hipMemcpyAsync(f_host, f64, 8 * (size_t)runs,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK && idx_host)
+    rc = from_hip(hipMemcpyAsync(idx_host, idx, 4 * (size_t)runs,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
   return rc;
 }
 

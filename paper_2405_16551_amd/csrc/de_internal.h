@@ -44,6 +44,10 @@ hipError_t launch_stats_reset(const GenArgs& a, bool reset_accepted,
                               hipStream_t s);
 hipError_t launch_best_from_fit(const GenArgs& a, hipStream_t s);
 hipError_t launch_mark_changed(const GenArgs& a, hipStream_t s);
+hipError_t launch_best_f64(const GenArgs& a, int kind, const float* rf32,
+                           double* f64, int* idx, hipStream_t s);
+hipError_t launch_copy_rot(const float* R, int ldr, int D, float* rf32,
+                           hipStream_t s);
 hipError_t launch_hit_check(const GenArgs& a, unsigned long long target_key,
                             hipStream_t s);
 hipError_t launch_debug_draws(const GenArgs& a, int* idx4, uint32_t* mask,

@@ -696,6 +696,59 @@ __global__ __launch_bounds__(256) void k_best_from_fit(GenArgs a) {
   if ((threadIdx.x % 64) == 0) atomicMin(&a.best_key[run], best);
 }
 
+// FP64 re-evaluation of each run's current best row (one workgroup per
+// run): the row is taken as the FP32 values it holds, y = x - o and, for the
+// rotated objective, z = R y with R the FP32 matrix the caller supplied, are
+// formed in FP64, and f is summed in a fixed order.  rf32 is R row-major
+// [D][D]; f64 and idx receive one value per run.
+__global__ __launch_bounds__(256) void k_best_f64(GenArgs a, int kind,
+                                                  const float* rf32,
+                                                  double* f64, int* idx) {
+  __shared__ double ys[4096];
+  __shared__ double red[256];
+  const int run = blockIdx.x;
+  const unsigned long long key = a.best_key[run];
+  const int i = (int)(key & 0xFFFFFFFFu);
+  const float* x = a.pop_cur + ((size_t)run * a.NP + i) * a.ldx;
+  double part = 0.0;
+  if (kind == kObjSphere) {
+    for (int j = threadIdx.x; j < a.D; j += 256) {
+      const double y = (double)x[j] - (double)a.o[j];
+      part = fma(y, y, part);
+    }
+  } else {
+    for (int j = threadIdx.x; j < a.D; j += 256)
+      ys[j] = (double)x[j] - (double)a.o[j];
+    __syncthreads();
+    for (int r = threadIdx.x; r < a.D; r += 256) {
+      double z = 0.0;
+      for (int j = 0; j < a.D; ++j)
+        z = fma((double)rf32[(size_t)j * a.D + r], ys[j], z);
+      const double sz = sin(3.0 * z);
+      part += fma(z, z, sz * sz);
+    }
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int m = 128; m >= 1; m >>= 1) {
+    if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    f64[run] = red[0];
+    idx[run] = i;
+  }
+}
+
+// Transposed FP32 copy of R (for the FP64 re-evaluation).
+__global__ __launch_bounds__(256) void k_copy_rot(const float* R, int ldr,
+                                                  int D, float* rf32) {
+  const size_t total = (size_t)D * D;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256)
+    rf32[t] = R[(t % D) * ldr + t / D];
+}
+
 // Runs whose current best is already <= target hit at generation `gen`.
 __global__ void k_hit_check(GenArgs a, unsigned long long target_key) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < a.runs;
@@ -874,6 +927,20 @@ hipError_t launch_mark_changed(const GenArgs& a, hipStream_t s) {
 hipError_t launch_best_from_fit(const GenArgs& a, hipStream_t s) {
   const int bx = grid_for(a.NP, 256) > 64 ? 64 : grid_for(a.NP, 256);
   hipLaunchKernelGGL(k_best_from_fit, dim3(bx, a.runs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_f64(const GenArgs& a, int kind, const float* rf32,
+                           double* f64, int* idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_best_f64, dim3(a.runs), dim3(256), 0, s, a, kind, rf32,
+                     f64, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rot(const float* R, int ldr, int D, float* rf32,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_rot, dim3(grid_for((size_t)D * D, 256)), dim3(256),
+                     0, s, R, ldr, D, rf32);
   return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ class de_buffers(ctypes.Structure):
 
 EXPORTS = ("de_abi_version", "de_strerror", "de_workspace_bytes",
            "de_init_population", "de_generation", "de_evolve", "de_best",
-           "de_get_generation", "de_read_stats", "de_load_population",
+           "de_best_f64", "de_get_generation", "de_read_stats", "de_load_population",
            "de_eval", "de_debug_draws", "de_destroy")
 
 
@@ -77,6 +77,8 @@ def _load():
     lib.de_best.restype = st
     lib.de_best.argtypes = [vp, i32, vp, P(ctypes.c_float),
                             P(ctypes.c_double), P(i32)]
+    lib.de_best_f64.restype = st
+    lib.de_best_f64.argtypes = [vp, vp, P(ctypes.c_double), P(i32)]
     lib.de_get_generation.restype = st
     lib.de_get_generation.argtypes = [vp, P(i64)]
     lib.de_read_stats.restype = st
@@ -153,6 +155,13 @@ def de_best(handle, run: int, stream, D: int):
     _check(_lib.de_best(handle, run, stream, x, ctypes.byref(f),
                         ctypes.byref(idx)), "de_best")
     return list(x), float(f.value), int(idx.value)
+
+
+def de_best_f64(handle, stream, runs: int):
+    f = (ctypes.c_double * runs)()
+    idx = (ctypes.c_int32 * runs)()
+    _check(_lib.de_best_f64(handle, stream, f, idx), "de_best_f64")
+    return [float(v) for v in f], [int(v) for v in idx]
 
 
 def de_get_generation(handle) -> int:
@@ -256,6 +265,10 @@ class DifferentialEvolution:
 
     def best(self, run: int = 0):
         return de_best(self.handle, run, self._s(), self.D)
+
+    def best_f64(self):
+        """FP64 objective of each run's best row: (values, indices)."""
+        return de_best_f64(self.handle, self._s(), self.runs)
 
     def stats(self):
         return de_read_stats(self.handle, self._s(), self.runs)

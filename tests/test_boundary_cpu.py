@@ -22,7 +22,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 13
+    assert len(names) == 14
     assert set(names) == set(d.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", d.LIB_PATH],
                          capture_output=True, text=True, check=True).stdout
@@ -98,9 +98,11 @@ def test_workspace_bytes_layout():
     st3, f32 = ws_status(P(), O(prec=0))
     assert st == st2 == st3 == d.DE_OK
     assert sep % 256 == 0 and bf % 256 == 0
-    # rotated adds R in the operand layout, D padded to 1024
-    assert bf - sep == 1024 * 1024 * 2
-    assert f32 - sep == 1024 * 1024 * 4
+    # rotated adds R in the operand layout (D padded to 1024) and an FP32
+    # row-major copy of R for the FP64 re-evaluation
+    copy = 1000 * 1000 * 4
+    assert bf - sep == 1024 * 1024 * 2 + copy
+    assert f32 - sep == 1024 * 1024 * 4 + copy
     assert d.de_workspace_bytes(P(), O(kind=0)) == sep
 
 
@@ -150,6 +152,7 @@ def test_calls_without_a_live_handle():
         assert lib.de_load_population(h, 0, None) == d.DE_E_STATE
         assert lib.de_eval(h, 16, 1, 4, 16, None) == d.DE_E_STATE
         assert lib.de_debug_draws(h, 0, None, None, None) == d.DE_E_STATE
+        assert lib.de_best_f64(h, None, ctypes.byref(dbl), None) == d.DE_E_STATE
     assert lib.de_destroy(None) == d.DE_OK
     assert lib.de_destroy(bogus) == d.DE_E_STATE
 

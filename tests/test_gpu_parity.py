@@ -263,6 +263,32 @@ def test_best_reports_lowest_value_lowest_index():
                                       host(de.population())[r, idx])
 
 
+@pytest.mark.parametrize("kind,prec,runs,NP,D,G", [
+    ("sphere", "fp32", 3, 40, 37, 30),
+    ("rot_osc", "fp32", 2, 64, 100, 20),
+    ("rot_osc", "bf16", 2, 64, 100, 20),
+    ("rot_osc", "bf16", 1, 128, 1000, 3),
+])
+def test_best_f64_matches_oracle(kind, prec, runs, NP, D, G):
+    # the FP64 re-evaluation of each run's best row equals the oracle's FP64
+    # objective of that FP32 row (up to summation order), and it bounds the
+    # error the generation step's own arithmetic made on that row
+    de, o, R = make_de(runs=runs, NP=NP, D=D, kind=kind, gemm_prec=prec)
+    de.generation(G)
+    pop = host(de.population()).astype(np.float64)
+    fit = host(de.fitness()).astype(np.float64)
+    f64, idx = de.best_f64()
+    for r in range(runs):
+        _, fb, ib = de.best(r)
+        assert idx[r] == ib
+        fo = oracle.objective(okind(kind), pop[r, idx[r]], o, R)
+        assert abs(f64[r] - fo) <= 1e-12 * fo
+        rtol = bf16_rtol(D) if prec == "bf16" else FP32_RTOL
+        assert abs(fit[r, idx[r]] - f64[r]) <= rtol * f64[r]
+        print(f"{kind}/{prec} D={D} run {r}: f32-path {fit[r, idx[r]]:.9e} "
+              f"fp64 {f64[r]:.9e} rel {abs(fit[r, idx[r]] - f64[r]) / f64[r]:.2e}")
+
+
 # ---------------------------------------------------------------------------
 # Whole runs: distributions over 30 runs against the oracle.
 
