@@ -65,9 +65,10 @@ def _load():
     lib.oracle_objective.restype = c_dbl
     lib.oracle_objective_batch.argtypes = [c_int, c_int, c_i64, dp, dp, dp,
                                            dp, c_int]
-    lib.oracle_init.argtypes = [c_int, c_int, c_int, c_dbl, c_dbl, c_u64, dp]
+    lib.oracle_init.argtypes = [c_int, c_int, c_int, c_int, c_dbl, c_dbl,
+                                c_u64, dp]
     lib.oracle_generation.argtypes = [
-        c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64, c_i64, c_int,
+        c_int, c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64, c_i64, c_int,
         dp, dp, dp, dp, dp, dp, dp, dp, i32p, i32p, c_int]
     lib.oracle_run.argtypes = [
         c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64, c_int, dp, dp,
@@ -148,15 +149,19 @@ def objective_batch(kind: int, X, o, R=None, nthreads: int = 1):
     return f
 
 
-def init_population(runs, NP, D, lo, hi, seed):
+def init_population(runs, NP, D, lo, hi, seed, run0: int = 0):
+    """Generation 0 of runs run0 .. run0 + runs - 1 (run numbers enter the
+    draw counter)."""
     pop = np.empty((runs, NP, D), dtype=np.float64)
-    _load().oracle_init(runs, NP, D, lo, hi, seed, _ptr(pop, ctypes.c_double))
+    _load().oracle_init(runs, run0, NP, D, lo, hi, seed,
+                        _ptr(pop, ctypes.c_double))
     return pop
 
 
 def generation(pop, fit, *, F, CR, lo, hi, seed, gen, kind, o, R=None,
-               nthreads: int = 1):
-    """One synchronous generation.  pop [runs,NP,D], fit [runs,NP] (FP64).
+               nthreads: int = 1, run0: int = 0):
+    """One synchronous generation.  pop [runs,NP,D], fit [runs,NP] (FP64);
+    run r of the arrays is run number run0 + r of the draw counters.
 
     Returns a dict with pop_next, fit_next, trial, ftrial, accept, draws.
     """
@@ -169,7 +174,7 @@ def generation(pop, fit, *, F, CR, lo, hi, seed, gen, kind, o, R=None,
                draws=np.empty((runs, NP, 4), dtype=np.int32))
     dpt = ctypes.c_double
     _load().oracle_generation(
-        runs, NP, D, F, CR, lo, hi, seed, gen, kind, _ptr(o, dpt),
+        runs, run0, NP, D, F, CR, lo, hi, seed, gen, kind, _ptr(o, dpt),
         _ptr(Rm, dpt), _ptr(pop, dpt), _ptr(fit, dpt),
         _ptr(out["pop_next"], dpt), _ptr(out["fit_next"], dpt),
         _ptr(out["trial"], dpt), _ptr(out["ftrial"], dpt),

@@ -193,14 +193,15 @@ void oracle_objective_batch(int kind, int D, int64_t n, const double* x,
 /* ---------------------------------------------------------------------- */
 /* Population initialisation (Section 2): x_ij uniform in the box,
  * x_ij = lo + u (hi - lo) with u = k * 2^-24 from the INIT stream, then
- * every individual is evaluated.  pop is [runs][NP][D].                   */
-void oracle_init(int runs, int NP, int D, double lo, double hi, uint64_t seed,
-                 double* pop) {
+ * every individual is evaluated.  pop is [runs][NP][D]; run r of the array
+ * uses run number run0 + r in the draw counter.                            */
+void oracle_init(int runs, int run0, int NP, int D, double lo, double hi,
+                 uint64_t seed, double* pop) {
   for (int r = 0; r < runs; ++r)
     for (int i = 0; i < NP; ++i)
       for (int j = 0; j < D; ++j) {
         uint32_t w[4];
-        or_draw(seed, OR_TAG_INIT, (uint32_t)r, 0u, (uint32_t)i,
+        or_draw(seed, OR_TAG_INIT, (uint32_t)(run0 + r), 0u, (uint32_t)i,
                 (uint32_t)(j >> 2), w);
         double u = (double)(w[j & 3] >> 8) * (1.0 / 16777216.0);
         pop[((size_t)r * NP + i) * D + j] = lo + u * (hi - lo);
@@ -214,9 +215,10 @@ void oracle_init(int runs, int NP, int D, double lo, double hi, uint64_t seed,
  *   selection  (Sec. 2): u replaces x iff f(u) < f(x)
  * pop/fit hold generation g; pop_next/fit_next receive g+1.  Optional
  * outputs (NULL to skip): trial [runs][NP][D], ftrial [runs][NP],
- * accept [runs][NP], draws [runs][NP][4].                                  */
-void oracle_generation(int runs, int NP, int D, double F, double CR, double lo,
-                       double hi, uint64_t seed, int64_t gen, int kind,
+ * accept [runs][NP], draws [runs][NP][4].  Run r of the arrays uses run
+ * number run0 + r in the draw counters (runs of a larger batch).           */
+void oracle_generation(int runs, int run0, int NP, int D, double F, double CR,
+                       double lo, double hi, uint64_t seed, int64_t gen, int kind,
                        const double* o, const double* R, const double* pop,
                        const double* fit, double* pop_next, double* fit_next,
                        double* trial, double* ftrial, int32_t* accept,
@@ -229,14 +231,14 @@ void oracle_generation(int runs, int NP, int D, double F, double CR, double lo,
     int r = (int)(t / NP), i = (int)(t % NP);
     const double* P = pop + (size_t)r * NP * D;
     int32_t d[4];
-    oracle_draw_indices(seed, r, gen, i, NP, D, d);
+    oracle_draw_indices(seed, run0 + r, gen, i, NP, D, d);
     const double* x = P + (size_t)i * D;
     const double* x1 = P + (size_t)d[0] * D;
     const double* x2 = P + (size_t)d[1] * D;
     const double* x3 = P + (size_t)d[2] * D;
     double* u = (double*)malloc(sizeof(double) * (size_t)D);
     for (int j = 0; j < D; ++j) {
-      if (oracle_take_mutant(seed, r, gen, i, j, d[3], CR)) {
+      if (oracle_take_mutant(seed, run0 + r, gen, i, j, d[3], CR)) {
         double v = x1[j] + F * (x2[j] - x3[j]);
         if (v < lo) v = lo;
         if (v > hi) v = hi;
@@ -282,7 +284,7 @@ int oracle_run(int runs, int NP, int D, double F, double CR, double lo,
     free(pa); free(pb); free(fa); free(fb); free(acc);
     return 1;
   }
-  oracle_init(runs, NP, D, lo, hi, seed, pa);
+  oracle_init(runs, 0, NP, D, lo, hi, seed, pa);
   oracle_objective_batch(kind, D, (int64_t)n, pa, o, R, fa, nthreads);
   for (int r = 0; r < runs; ++r) {
     hit_gen[r] = -1;
@@ -290,7 +292,7 @@ int oracle_run(int runs, int NP, int D, double F, double CR, double lo,
   }
   for (int64_t g = 0; g <= G; ++g) {
     if (g > 0) {
-      oracle_generation(runs, NP, D, F, CR, lo, hi, seed, g - 1, kind, o, R,
+      oracle_generation(runs, 0, NP, D, F, CR, lo, hi, seed, g - 1, kind, o, R,
                         pa, fa, pb, fb, NULL, NULL, acc, NULL, nthreads);
       double* t = pa; pa = pb; pb = t;
       t = fa; fa = fb; fb = t;

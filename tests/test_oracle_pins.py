@@ -326,6 +326,27 @@ def test_generation_follows_the_operators(kind):
             assert out["fit_next"][r, i] == (fu if acc else fit[r, i])
 
 
+def test_run_offset_selects_the_counter_run_field():
+    # a slice of a batch (run numbers run0 ..) equals the same runs of the
+    # whole batch: run r of the arrays draws with run number run0 + r
+    NP, D, seed = 9, 6, 5
+    full = oracle.init_population(5, NP, D, LO, HI, seed)
+    part = oracle.init_population(2, NP, D, LO, HI, seed, run0=3)
+    np.testing.assert_array_equal(part, full[3:5])
+    o, R = instances.make_instance("rot_osc", D, 1)
+    fit = oracle.objective_batch(1, full.reshape(-1, D), o, R).reshape(5, NP)
+    a = oracle.generation(full, fit, F=0.7, CR=0.4, lo=LO, hi=HI, seed=seed,
+                          gen=2, kind=1, o=o, R=R)
+    b = oracle.generation(full[3:5], fit[3:5], F=0.7, CR=0.4, lo=LO, hi=HI,
+                          seed=seed, gen=2, kind=1, o=o, R=R, run0=3)
+    for key in ("pop_next", "fit_next", "trial", "accept", "draws"):
+        np.testing.assert_array_equal(b[key], a[key][3:5])
+    # and the run field is the one the draw functions take
+    for i in range(NP):
+        assert tuple(b["draws"][1, i]) == oracle.draw_indices(seed, 4, 2, i,
+                                                              NP, D)
+
+
 def test_generation_reads_only_generation_g():
     # synchronous semantics: permuting which individuals were already
     # replaced cannot matter -> a generation is a pure function of (pop, fit)
