@@ -28,6 +28,7 @@ struct GenArgs {
   int runs, NP, D, ldx, dpad, nrows;
   float F, lo, hi, target;
   uint32_t cr_threshold, gen, key_lo, key_hi;
+  uint32_t run_base;  // rotated kernels: draw-counter run = run_base + run
 };
 
 size_t rot_lds_bytes_host(int prec, int dpad);

@@ -1,0 +1,496 @@
+// de_tile.hpp -- device code shared by the per-problem and the batched
+// generation kernels: vector helpers, the per-run statistics update and the
+// rotated-objective tile (build trials into LDS, Z = Y R^T on MFMA with the
+// objective fused, select and write).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "de_device.hpp"
+#include "de_internal.h"
+
+namespace de {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr unsigned long long kNoHit = ~0ull;
+
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) {
+  *reinterpret_cast<float4*>(p) = v;
+}
+__device__ __forceinline__ float get(const float4& v, int b) {
+  return b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ void set(float4& v, int b, float s) {
+  if (b == 0) v.x = s; else if (b == 1) v.y = s; else if (b == 2) v.z = s;
+  else v.w = s;
+}
+
+// Statistics after an accepted trial with value f of individual i in run r,
+// which produced generation gen+1.
+__device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
+                                              float f) {
+  atomicAdd(&a.accepted[run], 1ull);
+  atomicMin(&a.best_key[run], fit_key(f, i));
+  if (f <= a.target) {
+    const unsigned long long old =
+        atomicMin(&a.hit_gen[run], (unsigned long long)a.gen + 1ull);
+    if (old == kNoHit) atomicAdd(a.done, 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rotated objective.  Tile of BM trial rows per workgroup of NT threads.
+//   phase 1: donors of every row, then per row all target/donor loads in
+//            flight before the crossover draws; trial rows -> LDS A tile as
+//            y = u - o in the GEMM precision, crossover decisions -> bit
+//            planes; padding rows and columns are zero.
+//   phase 2: Z = Y R^T in 32x32 MFMA blocks, wave tile BM x 64 columns, R
+//            fragments prefetched four K-steps ahead from L2; the objective
+//            z^2 + sin^2(3z) is summed per row in registers.
+//   phase 3: row totals -> selection -> next generation rows (a rejected row
+//            is rewritten only if the other buffer holds a stale copy),
+//            statistics.
+struct PrecBF16 {
+  using T = __bf16;
+  static constexpr int kPad = 8;  // LDS row padding, elements
+};
+struct PrecF32 {
+  using T = float;
+  static constexpr int kPad = 4;
+};
+
+template <class P, int BM, int NT>
+__host__ __device__ constexpr size_t rot_lds_bytes(int dpad) {
+  const int tq = (dpad / 4 + 63) / 64;
+  return (size_t)BM * (dpad + P::kPad) * sizeof(typename P::T)  // A tile
+         + (size_t)BM * tq * 4 * sizeof(unsigned long long)     // planes
+         + (size_t)BM * 4 * sizeof(int)                         // donors
+         + (size_t)(NT / 64) * BM * sizeof(float);              // partials
+}
+
+// Position of coordinate k inside an LDS row.  BF16: natural order.  FP32:
+// within each group of 8, k = 2s + h is stored at 4h + s so that one lane's
+// four K-steps of the 32x32x2 MFMA are one 16-byte read.
+template <class P>
+__device__ __forceinline__ int lds_col(int k) {
+  if constexpr (sizeof(typename P::T) == 2) {
+    return k;
+  } else {
+    const int g = k & ~7, r = k & 7;
+    return g + (r & 1) * 4 + (r >> 1);
+  }
+}
+
+// One coordinate of the rotated oscillating objective: z^2 + sin^2(3z).
+// FP32 product: sin^2 from the reduction and series of sin_squared.
+// BF16 product (z already carries BF16 operand rounding, relative error
+// ~2^-8): the hardware sine, which takes its argument in turns; 3z / (2 pi)
+// is reduced to [-1/2, 1/2] turns first (exact), the remaining error is the
+// FP32 rounding of 3z / (2 pi), about 2^-24 |3z| radians.
+template <bool kFastSin>
+__device__ __forceinline__ float osc_term(float z) {
+  if constexpr (kFastSin) {
+    constexpr float kTurnsPer3z = 0x1.e8ec8ap-2f;  // 3 / (2 pi)
+    const float turns = z * kTurnsPer3z;
+    const float s = __builtin_amdgcn_sinf(turns - rintf(turns));
+    return fmaf(z, z, s * s);
+  } else {
+    return fmaf(z, z, sin_squared(3.0f * z));
+  }
+}
+
+template <bool kFastSin>
+__device__ __forceinline__ void osc_accumulate(floatx16& part,
+                                               const floatx16& c) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part[r] += osc_term<kFastSin>(c[r]);
+}
+
+// Target and donor chunks of one row, for a group of four 256-coordinate
+// chunks.
+struct RowChunks {
+  float4 xv[4], v1[4], v2[4], v3[4];
+};
+
+// R fragments of four consecutive K-steps for two column blocks.
+struct BFrags {
+  bf16x8 b0[4], b1[4];
+};
+
+__device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
+                                            const bf16x8* rb1, int kb) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    f.b0[u] = rb0[(size_t)(kb + u) * 64];
+    f.b1[u] = rb1[(size_t)(kb + u) * 64];
+  }
+}
+
+// Scheduling pattern for one K-step: its LDS reads (next A fragments) and
+// L2 loads (R fragments of a later step) are placed between its MFMAs
+// instead of in one burst, so the matrix unit keeps busy while they go out.
+template <int MB>
+__device__ __forceinline__ void interleave_step() {
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+  __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+  if constexpr (MB == 2) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Four FP32 K-steps (8 coordinates) of the wave tile, rows 0-31.
+__device__ __forceinline__ void f32_step(const float* ar, int k8, float4 b0,
+                                         float4 b1, floatx16& c00,
+                                         floatx16& c01) {
+  const float4 av = *reinterpret_cast<const float4*>(ar + k8 * 8);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b0.x, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b1.x, c01, 0, 0, 0);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b0.y, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b1.y, c01, 0, 0, 0);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b0.z, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b1.z, c01, 0, 0, 0);
+  c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b0.w, c00, 0, 0, 0);
+  c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b1.w, c01, 0, 0, 0);
+}
+
+// One tile: rows row0 .. row0 + nvalid - 1 of run `run` (EVAL: of the
+// flattened row range).  Ends with every LDS access of the tile complete
+// only for the calling thread: a caller that runs another tile in the same
+// workgroup synchronises first.
+template <class P, int BM, int NT, bool EVAL>
+__device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
+                                         int nvalid) {
+  using T = typename P::T;
+  constexpr int MB = BM / 32;
+  constexpr int kRotThreads = NT;
+  constexpr int kRotWaves = NT / 64;
+  static_assert(MB == 1 || (MB == 2 && sizeof(T) == 2), "tile shape");
+  extern __shared__ __align__(16) char smem[];
+  const int dpad = a.dpad;
+  const int stride = dpad + P::kPad;
+  const int tq = (dpad / 4 + 63) / 64;
+  T* At = reinterpret_cast<T*>(smem);
+  unsigned long long* planes = reinterpret_cast<unsigned long long*>(
+      smem + (size_t)BM * stride * sizeof(T));
+  int* donors = reinterpret_cast<int*>(planes + (size_t)BM * tq * 4);
+  float* fpart = reinterpret_cast<float*>(donors + BM * 4);
+
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const uint32_t rng_run = a.run_base + (uint32_t)run;
+  const float* base = a.pop_cur + (EVAL ? 0 : (size_t)run * a.NP * a.ldx);
+
+  // ---- phase 1: build the A tile
+  if (!EVAL) {
+    for (int rl = (int)threadIdx.x; rl < nvalid; rl += kRotThreads) {
+      const Donors d = pick_donors(rng_run, a.gen, row0 + rl, a.NP, a.D,
+                                   a.key_lo, a.key_hi);
+      donors[rl * 4 + 0] = d.r1;
+      donors[rl * 4 + 1] = d.r2;
+      donors[rl * 4 + 2] = d.r3;
+      donors[rl * 4 + 3] = d.jrand;
+    }
+    __syncthreads();
+  }
+  // Rows rl = wave + kRotWaves * k of this wave; each row is cut into groups
+  // of four 256-coordinate chunks.  Items (row, group) are processed in
+  // order with two register sets, so the loads of item s + 1 are in flight
+  // while item s is drawn, mutated and stored.
+  for (int rl = nvalid + (((wave - nvalid) % kRotWaves) + kRotWaves) %
+                             kRotWaves;
+       rl < BM; rl += kRotWaves) {
+    T* arow = At + (size_t)rl * stride;
+    for (int k = lane; k < dpad; k += 64) arow[k] = (T)0.0f;
+  }
+  {
+    // Rows rl = wave + kRotWaves * k of this wave, two rows per step: the
+    // target and donor chunks of both rows (groups of four 256-coordinate
+    // chunks) are requested together, then drawn, mutated and stored.
+    // Loads past the end of a row go to its last chunk (values unused), so
+    // no load sits behind a per-lane branch.
+    const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
+    const int dlast = ((a.D + 3) / 4 - 1) * 4;
+    for (int t0 = 0; t0 < tq; t0 += 4) {
+      float4 ov[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        ov[u] = ld4(a.o + min(4 * (lane + 64 * (t0 + u)), dlast));
+      for (int k = 0; k < nrow_w; k += 2) {
+        const bool two = k + 1 < nrow_w;
+        RowChunks c[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rl = wave + kRotWaves * (two ? k + h : k);
+          const float* xrow = base + (size_t)(row0 + rl) * a.ldx;
+          const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
+          if (!EVAL) {
+            x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
+            x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
+            x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int jl = min(4 * (lane + 64 * (t0 + u)), dlast);
+            c[h].xv[u] = ld4(xrow + jl);
+            if (!EVAL) {
+              c[h].v1[u] = ld4(x1 + jl);
+              c[h].v2[u] = ld4(x2 + jl);
+              c[h].v3[u] = ld4(x3 + jl);
+            }
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && !two) break;
+          const int rl = wave + kRotWaves * (k + h);
+          const int i = row0 + rl;
+          const int jrand = EVAL ? 0 : donors[rl * 4 + 3];
+          T* arow = At + (size_t)rl * stride;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            if (t >= tq) break;
+            const int q = lane + 64 * t, j0 = 4 * q;
+            uint32_t bits = 0;
+            float4 uu = c[h].xv[u];
+            if (!EVAL) {
+              const Words4 w = draw_block(kTagXover, rng_run, a.gen,
+                                          (uint32_t)i, (uint32_t)q, a.key_lo,
+                                          a.key_hi);
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const bool tk =
+                    (j0 + b < a.D) &&
+                    take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold);
+                const float mv =
+                    mutant_coord(get(c[h].v1[u], b), get(c[h].v2[u], b),
+                                 get(c[h].v3[u], b), a.F, a.lo, a.hi);
+                set(uu, b, tk ? mv : get(c[h].xv[u], b));
+                bits |= (tk ? 1u : 0u) << b;
+              }
+            }
+            float4 y;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              set(y, b, (j0 + b < a.D) ? get(uu, b) - get(ov[u], b) : 0.f);
+            if (j0 < dpad) {
+              if constexpr (sizeof(T) == 2) {
+                bf16x4 yb;
+                yb[0] = (__bf16)y.x;
+                yb[1] = (__bf16)y.y;
+                yb[2] = (__bf16)y.z;
+                yb[3] = (__bf16)y.w;
+                *reinterpret_cast<bf16x4*>(arow + j0) = yb;
+              } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                  arow[lds_col<P>(j0 + b)] = get(y, b);
+              }
+            }
+            if (!EVAL) {
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const unsigned long long m = __ballot((bits >> b) & 1u);
+                if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: Z = Y R^T with the objective fused into the epilogue
+  // Accumulators c{m}{n}: 32x32 block (row block m, column block nb0 + n),
+  // named values rather than arrays so that every index is static.
+  // Wave w of every workgroup streams the same R fragments at about the same
+  // time, so concurrent requests from the CUs of an XCD share L2 lines.
+  const int nblk = dpad / 32;
+  floatx16 part0 = {}, part1 = {};
+  for (int nb0 = wave * 2; nb0 < nblk; nb0 += kRotWaves * 2) {
+    floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
+    if constexpr (sizeof(T) == 2) {
+      // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per
+      // block and K-step; dpad / 16 is a multiple of 4.
+      const bf16x8* rop = reinterpret_cast<const bf16x8*>(a.rop);
+      const int kbn = dpad / 16;
+      const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
+      const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
+      const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
+      // Software pipeline at K-step granularity: the A fragments of step
+      // k + 1 are read from LDS while step k's MFMAs run (two slots), and
+      // the R fragments of the next four-step group are loaded from L2 one
+      // pair per step into the other of two register sets.  Each step's
+      // reads are interleaved with its four MFMAs.  dpad / 16 is a multiple
+      // of 8.
+      const T* ar1 = ar + (size_t)32 * stride;
+      bf16x8 a0s[2], a1s[2];
+      BFrags fa, fb;
+      a0s[0] = *reinterpret_cast<const bf16x8*>(ar);
+      if constexpr (MB == 2) a1s[0] = *reinterpret_cast<const bf16x8*>(ar1);
+      load_bfrags(fa, rb0, rb1, 0);
+      for (int kb = 0; kb < kbn; kb += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = kb + u;
+          const int cur = u & 1, nxt = cur ^ 1;
+          if (u < 7 || k + 1 < kbn) {
+            a0s[nxt] = *reinterpret_cast<const bf16x8*>(ar + (k + 1) * 16);
+            if constexpr (MB == 2)
+              a1s[nxt] = *reinterpret_cast<const bf16x8*>(ar1 + (k + 1) * 16);
+          }
+          if (u < 4) {
+            fb.b0[u] = rb0[(size_t)(kb + 4 + u) * 64];
+            fb.b1[u] = rb1[(size_t)(kb + 4 + u) * 64];
+          } else if (kb + 8 < kbn) {
+            fa.b0[u - 4] = rb0[(size_t)(kb + 8 + u - 4) * 64];
+            fa.b1[u - 4] = rb1[(size_t)(kb + 8 + u - 4) * 64];
+          }
+          const bf16x8 b0 = u < 4 ? fa.b0[u & 3] : fb.b0[u & 3];
+          const bf16x8 b1 = u < 4 ? fa.b1[u & 3] : fb.b1[u & 3];
+          c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b0, c00, 0, 0,
+                                                        0);
+          c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b1, c01, 0, 0,
+                                                        0);
+          if constexpr (MB == 2) {
+            c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b0, c10, 0,
+                                                          0, 0);
+            c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b1, c11, 0,
+                                                          0, 0);
+          }
+          interleave_step<MB>();
+        }
+      }
+    } else {
+      // R as [nblk][dpad/8][64 lanes][4]: one float4 = four K-steps;
+      // dpad / 8 is a multiple of 2.
+      const float4* rop = reinterpret_cast<const float4*>(a.rop);
+      const int k8n = dpad / 8;
+      const float4* rb0 = rop + ((size_t)nb0 * k8n) * 64 + lane;
+      const float4* rb1 = rb0 + (size_t)k8n * 64;
+      const float* ar = reinterpret_cast<const float*>(At) +
+                        (size_t)(lane % 32) * stride + 4 * (lane / 32);
+      float4 p00 = rb0[0], p01 = rb0[64], p10 = rb1[0], p11 = rb1[64];
+      for (int k8 = 0; k8 < k8n; k8 += 2) {
+        const float4 q00 = p00, q01 = p01, q10 = p10, q11 = p11;
+        if (k8 + 2 < k8n) {
+          const size_t nx = (size_t)(k8 + 2) * 64;
+          p00 = rb0[nx];
+          p01 = rb0[nx + 64];
+          p10 = rb1[nx];
+          p11 = rb1[nx + 64];
+        }
+        f32_step(ar, k8 + 0, q00, q10, c00, c01);
+        f32_step(ar, k8 + 1, q01, q11, c00, c01);
+      }
+    }
+    constexpr bool kFastSin = sizeof(T) == 2;
+    osc_accumulate<kFastSin>(part0, c00);
+    osc_accumulate<kFastSin>(part0, c01);
+    if constexpr (MB == 2) {
+      osc_accumulate<kFastSin>(part1, c10);
+      osc_accumulate<kFastSin>(part1, c11);
+    }
+  }
+  // 32x32 accumulator layout: register r of lane l holds row
+  // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.  Each lane
+  // has 32 per-row partial sums (value v = 16 m + r); a reduce-scatter
+  // butterfly over the 32 lanes of each half-wave leaves lane l with the
+  // total of value v = l % 32 (31 exchanges instead of 5 per value).
+  {
+    float v[32];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      v[r] = part0[r];
+      v[16 + r] = MB == 2 ? part1[r] : 0.f;
+    }
+#pragma unroll
+    for (int m = 16, n = 32; m >= 1; m >>= 1, n >>= 1) {
+      const bool upper = (lane & m) != 0;
+#pragma unroll
+      for (int k = 0; k < n / 2; ++k) {
+        const float send = upper ? v[k] : v[k + n / 2];
+        const float keep = upper ? v[k + n / 2] : v[k];
+        v[k] = keep + __shfl_xor(send, m, 64);
+      }
+    }
+    const int idx = lane % 32, mb = idx / 16, r = idx % 16;
+    const int row = mb * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+    if (mb < MB) fpart[wave * BM + row] = v[0];
+  }
+  __syncthreads();
+
+  // ---- phase 3: selection and the next generation
+  for (int rl = wave; rl < nvalid; rl += kRotWaves) {
+    float f = 0.f;
+#pragma unroll
+    for (int w = 0; w < kRotWaves; ++w) f += fpart[w * BM + rl];
+    const int i = row0 + rl;
+    if (EVAL) {
+      if (lane == 0) a.fit_next[i] = f;
+      continue;
+    }
+    const size_t g = (size_t)run * a.NP + i;
+    const float fx = a.fit_cur[g];
+    const bool accept = f < fx;
+    const bool refresh = !accept && a.changed[g] != 0;
+    if (accept || refresh) {
+      const float* xrow = base + (size_t)i * a.ldx;
+      float* nrow = a.pop_next + g * a.ldx;
+      const float* x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
+      const float* x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
+      const float* x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+      const int dlast = ((a.D + 3) / 4 - 1) * 4;
+      for (int t0 = 0; t0 < tq; t0 += 4) {
+        float4 xv[4], v1[4], v2[4], v3[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jl = min(4 * (lane + 64 * (t0 + u)), dlast);
+          xv[u] = ld4(xrow + jl);
+          if (accept) {
+            v1[u] = ld4(x1 + jl);
+            v2[u] = ld4(x2 + jl);
+            v3[u] = ld4(x3 + jl);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + u;
+          if (t >= tq) break;
+          const int j0 = 4 * (lane + 64 * t);
+          float4 out = xv[u];
+          if (accept) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const unsigned long long m = planes[((size_t)rl * tq + t) * 4 + b];
+              const float mv = mutant_coord(get(v1[u], b), get(v2[u], b),
+                                            get(v3[u], b), a.F, a.lo, a.hi);
+              set(out, b, ((m >> lane) & 1ull) ? mv : get(xv[u], b));
+            }
+          }
+          if (j0 < a.D) st4(nrow + j0, out);
+        }
+      }
+    }
+    if (lane == 0) {
+      a.fit_next[g] = accept ? f : fx;
+      a.changed[g] = accept ? 1 : 0;
+      if (accept) record_accept(a, run, i, f);
+    }
+  }
+}
+
+}  // namespace de

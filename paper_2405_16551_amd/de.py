@@ -44,10 +44,38 @@ class de_buffers(ctypes.Structure):
                 ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
 
 
+class de_run_spec(ctypes.Structure):
+    _fields_ = [("NP", ctypes.c_int32), ("D", ctypes.c_int32),
+                ("F", ctypes.c_float), ("CR", ctypes.c_float)]
+
+
+class de_batch_instance(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("ldr", ctypes.c_int32),
+                ("o", ctypes.c_void_p), ("R", ctypes.c_void_p)]
+
+
+class de_batch_params(ctypes.Structure):
+    _fields_ = [("nruns", ctypes.c_int32), ("ninst", ctypes.c_int32),
+                ("runs", ctypes.POINTER(de_run_spec)),
+                ("inst", ctypes.POINTER(de_batch_instance)),
+                ("lo", ctypes.c_float), ("hi", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("gemm_prec", ctypes.c_int32),
+                ("graph_gens", ctypes.c_int32), ("target", ctypes.c_double)]
+
+
+DE_BATCH_AUTO, DE_BATCH_TILE64, DE_BATCH_TILE32, DE_BATCH_WIDE = -1, 0, 1, 2
+DE_BATCH_NVARIANTS = 3
+VARIANT_NAMES = {DE_BATCH_TILE64: "tile64", DE_BATCH_TILE32: "tile32",
+                 DE_BATCH_WIDE: "wide"}
+
 EXPORTS = ("de_abi_version", "de_strerror", "de_workspace_bytes",
            "de_init_population", "de_generation", "de_evolve", "de_best",
            "de_best_f64", "de_get_generation", "de_read_stats", "de_load_population",
-           "de_eval", "de_debug_draws", "de_destroy")
+           "de_eval", "de_debug_draws", "de_destroy",
+           # include/de_batch.h
+           "de_batch_layout", "de_batch_create", "de_batch_plan",
+           "de_batch_generation", "de_batch_read", "de_batch_get_generation",
+           "de_batch_destroy")
 
 
 def _load():
@@ -91,6 +119,24 @@ def _load():
     lib.de_debug_draws.argtypes = [vp, i64, vp, vp, vp]
     lib.de_destroy.restype = st
     lib.de_destroy.argtypes = [vp]
+    szp = P(ctypes.c_size_t)
+    lib.de_batch_layout.restype = st
+    lib.de_batch_layout.argtypes = [P(de_batch_params), P(i64), P(i32), P(i64),
+                                    szp, szp, szp]
+    lib.de_batch_create.restype = st
+    lib.de_batch_create.argtypes = [P(de_batch_params), vp, vp, vp, vp, vp,
+                                    ctypes.c_size_t, P(i32), vp, P(vp)]
+    lib.de_batch_plan.restype = st
+    lib.de_batch_plan.argtypes = [vp, P(i32), P(ctypes.c_float)]
+    lib.de_batch_generation.restype = st
+    lib.de_batch_generation.argtypes = [vp, i64, vp]
+    lib.de_batch_read.restype = st
+    lib.de_batch_read.argtypes = [vp, vp, P(ctypes.c_double), P(i32), P(i64),
+                                  P(i64)]
+    lib.de_batch_get_generation.restype = st
+    lib.de_batch_get_generation.argtypes = [vp, P(i64)]
+    lib.de_batch_destroy.restype = st
+    lib.de_batch_destroy.argtypes = [vp]
     return lib
 
 
@@ -192,6 +238,67 @@ def de_debug_draws(handle, gen: int, idx4_ptr, mask_ptr, stream):
 
 def de_destroy(handle):
     _check(_lib.de_destroy(handle), "de_destroy")
+
+
+def de_batch_layout(params: de_batch_params):
+    n = params.nruns
+    pop_off = (ctypes.c_int64 * n)()
+    ldx = (ctypes.c_int32 * n)()
+    fit_off = (ctypes.c_int64 * n)()
+    pf, ff, wb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.de_batch_layout(ctypes.byref(params), pop_off, ldx, fit_off,
+                                ctypes.byref(pf), ctypes.byref(ff),
+                                ctypes.byref(wb)), "de_batch_layout")
+    return dict(pop_off=list(pop_off), ldx=list(ldx), fit_off=list(fit_off),
+                pop_floats=int(pf.value), fit_floats=int(ff.value),
+                work_bytes=int(wb.value))
+
+
+def de_batch_create(params, pop0, pop1, fit0, fit1, work, work_bytes, plan,
+                    stream):
+    h = ctypes.c_void_p()
+    pl = None
+    if plan is not None:
+        pl = (ctypes.c_int32 * len(plan))(*plan)
+    _check(_lib.de_batch_create(ctypes.byref(params), pop0, pop1, fit0, fit1,
+                                work, work_bytes, pl, stream, ctypes.byref(h)),
+           "de_batch_create")
+    return h
+
+
+def de_batch_plan(handle, ninst: int):
+    plan = (ctypes.c_int32 * ninst)()
+    us = (ctypes.c_float * (ninst * DE_BATCH_NVARIANTS))()
+    _check(_lib.de_batch_plan(handle, plan, us), "de_batch_plan")
+    return list(plan), [list(us[k * DE_BATCH_NVARIANTS:(k + 1) * DE_BATCH_NVARIANTS])
+                        for k in range(ninst)]
+
+
+def de_batch_generation(handle, n_gens: int, stream):
+    _check(_lib.de_batch_generation(handle, n_gens, stream),
+           "de_batch_generation")
+
+
+def de_batch_read(handle, stream, nruns: int):
+    best = (ctypes.c_double * nruns)()
+    idx = (ctypes.c_int32 * nruns)()
+    acc = (ctypes.c_int64 * nruns)()
+    hit = (ctypes.c_int64 * nruns)()
+    _check(_lib.de_batch_read(handle, stream, best, idx, acc, hit),
+           "de_batch_read")
+    return dict(best_f=list(best), best_idx=list(idx), accepted=list(acc),
+                hit_gen=list(hit))
+
+
+def de_batch_get_generation(handle) -> int:
+    g = ctypes.c_int64(0)
+    _check(_lib.de_batch_get_generation(handle, ctypes.byref(g)),
+           "de_batch_get_generation")
+    return int(g.value)
+
+
+def de_batch_destroy(handle):
+    _check(_lib.de_batch_destroy(handle), "de_batch_destroy")
 
 
 # ---- owner of the caller-side buffers --------------------------------------
@@ -306,3 +413,96 @@ class DifferentialEvolution:
         mask = torch.empty((self.runs, self.NP, nw), dtype=torch.int32, device=self.device)
         de_debug_draws(self.handle, gen, idx.data_ptr(), mask.data_ptr(), self._s())
         return idx, mask
+
+
+class DEBatch:
+    """Many independent rotated-objective runs of mixed size (de_batch.h).
+
+    ``specs``: sequence of (NP, D, F, CR).  ``instances``: dict D -> (o, R)
+    (arrays, D floats and D x D row-major), one per distinct D.
+    ``plan``: None (autotune), or a dict D -> variant (DE_BATCH_*).
+    """
+
+    def __init__(self, specs, instances, *, lo=-100.0, hi=100.0, seed=1,
+                 graph_gens=16, target=1e-8, plan=None, device="cuda",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.specs = [(int(a), int(b), float(c), float(e)) for a, b, c, e in specs]
+        self.nruns = len(self.specs)
+        dims = sorted(instances)
+        self.dims = dims
+        dev = self.device
+        self._o = [torch.as_tensor(instances[D][0], dtype=torch.float32).to(dev).contiguous()
+                   for D in dims]
+        self._R = [torch.as_tensor(instances[D][1], dtype=torch.float32).to(dev).contiguous()
+                   for D in dims]
+        self._runs = (de_run_spec * self.nruns)(*[de_run_spec(*s) for s in self.specs])
+        self._inst = (de_batch_instance * len(dims))(
+            *[de_batch_instance(D, D, o.data_ptr(), R.data_ptr())
+              for D, o, R in zip(dims, self._o, self._R)])
+        self.params = de_batch_params(self.nruns, len(dims), self._runs,
+                                      self._inst, float(lo), float(hi),
+                                      int(seed), DE_GEMM_BF16, int(graph_gens),
+                                      float(target))
+        lay = de_batch_layout(self.params)
+        self.layout = lay
+        self.pop = [torch.zeros(max(lay["pop_floats"], 1), dtype=torch.float32,
+                                device=dev) for _ in range(2)]
+        self.fit = [torch.zeros(max(lay["fit_floats"], 1), dtype=torch.float32,
+                                device=dev) for _ in range(2)]
+        wb = lay["work_bytes"]
+        self.work = torch.zeros(wb + 256, dtype=torch.uint8, device=dev)
+        wptr = (self.work.data_ptr() + 255) // 256 * 256
+        pl = None
+        if plan is not None:
+            pl = [int(plan.get(D, DE_BATCH_AUTO)) for D in dims]
+        self.handle = de_batch_create(
+            self.params, self.pop[0].data_ptr(), self.pop[1].data_ptr(),
+            self.fit[0].data_ptr(), self.fit[1].data_ptr(), wptr, wb, pl,
+            self._s())
+        # instance data was converted into the workspace
+        del self._o, self._R
+
+    def _s(self):
+        return self.stream.cuda_stream
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            de_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def gen(self) -> int:
+        return de_batch_get_generation(self.handle)
+
+    def generation(self, n: int = 1):
+        de_batch_generation(self.handle, n, self._s())
+
+    def read(self):
+        return de_batch_read(self.handle, self._s(), self.nruns)
+
+    def plan(self):
+        """(variant per D, tuner microseconds per D and variant)."""
+        plan, us = de_batch_plan(self.handle, len(self.dims))
+        return dict(zip(self.dims, plan)), dict(zip(self.dims, us))
+
+    def population(self, run: int, gen=None):
+        """View [NP, D] of run `run` in generation gen (current by default)."""
+        g = self.gen if gen is None else gen
+        NP, D = self.specs[run][0], self.specs[run][1]
+        off, ldx = self.layout["pop_off"][run], self.layout["ldx"][run]
+        return self.pop[g & 1][off:off + NP * ldx].view(NP, ldx)[:, :D]
+
+    def fitness(self, run: int, gen=None):
+        g = self.gen if gen is None else gen
+        off = self.layout["fit_off"][run]
+        return self.fit[g & 1][off:off + self.specs[run][0]]

@@ -49,3 +49,27 @@ def make_instance(kind: str, D: int, obj_seed: int = 1):
     if kind == "rot_osc":
         return o, make_rotation(D, obj_seed)
     raise ValueError(f"unknown objective kind {kind!r}")
+
+
+MIXED_NP = (32, 64, 128, 256, 512, 1024)
+MIXED_D = (10, 30, 50, 100, 500)
+
+
+def make_mixed_specs(nruns: int, seed: int = 1, NPs=MIXED_NP, Ds=MIXED_D,
+                     F_range=(0.4, 0.9), CR_range=(0.1, 1.0)):
+    """Run sizes and control parameters of a mixed batch: NP and D drawn
+    uniformly from the given sets, F ~ U[F_range], CR ~ U[CR_range], all
+    per run and rounded to float32.  Returns a list of (NP, D, F, CR)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 7]))
+    NP = rng.choice(np.asarray(NPs), size=nruns)
+    D = rng.choice(np.asarray(Ds), size=nruns)
+    F = rng.uniform(*F_range, size=nruns).astype(np.float32)
+    CR = rng.uniform(*CR_range, size=nruns).astype(np.float32)
+    return [(int(a), int(b), float(c), float(e))
+            for a, b, c, e in zip(NP, D, F, CR)]
+
+
+def make_mixed_instances(specs, obj_seed: int = 1):
+    """One rotated-objective instance (o, R) per distinct D of `specs`."""
+    return {D: make_instance("rot_osc", D, obj_seed)
+            for D in sorted({s[1] for s in specs})}

@@ -52,13 +52,14 @@ def rounding_band(kind, u, o, R, tol):
 
 
 def compare_generation(gpu_pop, gpu_fit, pop32, fit_gpu_prev, *, F, CR, seed,
-                       gen, kind, o, R, f_rtol, rows=None):
+                       gen, kind, o, R, f_rtol, rows=None, run0=0):
     """Compare one GPU generation g -> g+1 with the oracle's, started from
     the same FP32 population.  Returns (n_rows_compared, n_near_ties).
 
     gpu_pop [runs,NP,D] / gpu_fit [runs,NP]: GPU generation g+1.
     pop32 [runs,NP,D]: generation g (FP32, shared input).
     fit_gpu_prev: GPU fitness of generation g (the targets' f on the GPU).
+    run0: run number of the first run (draw counter), for runs of a batch.
 
     Checks: the GPU's target fitness and the GPU's accepted trial's fitness
     against the oracle's FP64 evaluation of the same FP32 vectors (f_rtol);
@@ -73,7 +74,8 @@ def compare_generation(gpu_pop, gpu_fit, pop32, fit_gpu_prev, *, F, CR, seed,
                                    nthreads=8).reshape(runs, NP)
     np.testing.assert_allclose(fit_gpu_prev, fit64, rtol=f_rtol, atol=1e-30)
     out = oracle.generation(pop64, fit64, F=F, CR=CR, lo=LO, hi=HI, seed=seed,
-                            gen=gen, kind=kind, o=o, R=R, nthreads=8)
+                            gen=gen, kind=kind, o=o, R=R, nthreads=8,
+                            run0=run0)
     ties = 0
     n = 0
     it = rows if rows is not None else [(r, i) for r in range(runs)

@@ -13,16 +13,25 @@ import paper_2405_16551_amd.de as d
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "de.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("de.h", "de_batch.h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    return re.findall(r"DE_API\s+[\w\s\*]+?\b(de_\w+)\s*\(", src)
+    names = []
+    for h in HEADERS:
+        names += re.findall(r"DE_API\s+[\w\s\*]+?\b(de_\w+)\s*\(",
+                            open(h).read())
+    return names
+
+
+def test_every_header_is_covered():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == sorted(
+        os.path.basename(h) for h in HEADERS)
 
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 14
+    assert len(names) == 21
     assert set(names) == set(d.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", d.LIB_PATH],
                          capture_output=True, text=True, check=True).stdout
