@@ -12,8 +12,9 @@ steps (inputs resident in HBM).  Also reported: generations per second,
 the roofline position of the generation kernel (HIP events around every
 launch, algorithmic FLOPs 2 D^2 per trial), a separable companion workload
 (shifted sphere, same sizes; HBM roofline), wall time to the 1e-8 target
-on the small sphere workload (Section 7.3.4 early stopping), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+on the small sphere workload (Section 7.3.4 early stopping), a batch of 512
+independent runs of mixed NP, D, F and CR advanced by graph replays, and
+the FP64 CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -70,7 +71,7 @@ def algorithmic(w, trials, accept_rate):
 def kernel_sources_sha256():
     csrc = os.path.join(ROOT, "paper_2405_16551_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("de_kernels.hip", "de_device.hpp", "de_internal.h"):
+    for f in ("de_kernels.hip", "de_tile.hpp", "de_device.hpp", "de_internal.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -147,6 +148,69 @@ def time_workload(name, steps, warmup, seed=1):
                 best_vs_fp64=dict(max_rel_err=float(f"{max(rel):.3e}"),
                                   median_rel_err=float(
                                       f"{sorted(rel)[len(rel) // 2]:.3e}")))
+
+
+MIXED_RUNS = 512
+MIXED_GRAPH_GENS = 16
+
+
+def describe_mixed(nruns=MIXED_RUNS):
+    return (f"DE/rand/1/bin, {nruns} independent runs of mixed size: NP from "
+            "{32,64,128,256,512,1024}, D from {10,30,50,100,500}, F ~ "
+            "U[0.4,0.9], CR ~ U[0.1,1.0] per run, rotated oscillating, bf16 "
+            f"rotation product, autotuned tiles, {MIXED_GRAPH_GENS} generations "
+            "per graph launch")
+
+
+def time_batch(steps, warmup, nruns=MIXED_RUNS, graph_gens=MIXED_GRAPH_GENS):
+    """The mixed batch: every run advances one generation per step; timed
+    with HIP events on the batch's stream around whole graph replays."""
+    import torch
+
+    from paper_2405_16551_amd import instances
+    from paper_2405_16551_amd.de import VARIANT_NAMES, DEBatch
+
+    specs = instances.make_mixed_specs(nruns, seed=1)
+    inst = instances.make_mixed_instances(specs, 1)
+    t0 = time.perf_counter()
+    b = DEBatch(specs, inst, graph_gens=graph_gens, seed=1)
+    create_s = time.perf_counter() - t0
+    steps = max(graph_gens, (steps + graph_gens - 1) // graph_gens * graph_gens)
+    warm = max(graph_gens, (warmup + graph_gens - 1) // graph_gens * graph_gens)
+    b.generation(warm)
+    torch.cuda.synchronize()
+    acc0 = sum(b.read()["accepted"])
+    stream = b.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.generation(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    st = b.read()
+    trials = sum(s[0] for s in specs)
+    flops = sum(2.0 * s[0] * s[1] * s[1] for s in specs)
+    plan, us = b.plan()
+    b.close()
+    achieved = flops / (ms * 1e-3) / 1e12
+    return dict(
+        workload=describe_mixed(nruns), runs=nruns, trials_per_gen=trials,
+        steps=steps, warmup=warm, gens_per_s=round(steps / wall, 2),
+        evals_per_s=round(trials * steps / wall, 1),
+        ms_per_gen=round(ms, 5), wall_s=wall,
+        accept_rate=round((sum(st["accepted"]) - acc0) / (trials * steps), 4),
+        roofline=dict(bound="mfma", achieved=round(achieved, 3),
+                      peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=round(achieved / BF16_PEAK_TFLOPS, 4),
+                      traffic=None,
+                      scope="all kernels of one generation (2 D^2 FLOPs "
+                            "per trial, unpadded)"),
+        plan={str(D): VARIANT_NAMES[v] for D, v in plan.items()},
+        tuner_us={str(D): [round(t, 1) for t in ts] for D, ts in us.items()},
+        create_s=round(create_s, 3))
 
 
 def copy_ceiling(nbytes=1 << 30, reps=20):
@@ -229,7 +293,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot1000_bf16",
-                    choices=sorted(WORKLOADS))
+                    choices=sorted(WORKLOADS) + ["mixed512"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -246,6 +310,20 @@ def main():
 
     if args.copy_calibration:
         copy_ceiling(nbytes=256 << 20, reps=1)
+    if args.workload == "mixed512":
+        r = time_batch(args.steps, args.warmup)
+        print(json.dumps({
+            "metric": "trial evals/sec and gens/sec of a mixed batch "
+                      "(% roofline)",
+            "value": r["evals_per_s"], "unit": "trial evals/s", "n_gpus": 1,
+            "steps": r["steps"], "warmup": r["warmup"],
+            "ms_per_step": round(r["wall_s"] / r["steps"] * 1e3, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": r["workload"], "runs": r["runs"]},
+            "gens_per_s": r["gens_per_s"], "roofline": r["roofline"],
+            "plan": r["plan"], "tuner_us": r["tuner_us"]}), flush=True)
+        return
     main_res = time_workload(args.workload, args.steps, args.warmup)
     w = WORKLOADS[args.workload]
     line = {
@@ -280,6 +358,7 @@ def main():
             "gens_per_s": round(c["gens_per_s"], 2),
             "kernel_ms_per_step": round(c["kernel_ms"], 5),
             "accept_rate": c["accept_rate"], "roofline": c["roofline"]}
+        line["batched"] = time_batch(max(64, args.steps // 4), args.warmup)
         line["time_to_target"] = time_to_target()
         line["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
