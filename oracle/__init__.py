@@ -70,6 +70,10 @@ def _load():
     lib.oracle_generation.argtypes = [
         c_int, c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64, c_i64, c_int,
         dp, dp, dp, dp, dp, dp, dp, dp, i32p, i32p, c_int]
+    lib.oracle_jde_generation.argtypes = [
+        c_int, c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl,
+        c_u64, c_i64, c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+        i32p, dp, dp, c_int]
     lib.oracle_run.argtypes = [
         c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64, c_int, dp, dp,
         c_i64, c_dbl, dp, i64p, i64p, dp, dp, c_int]
@@ -181,6 +185,61 @@ def generation(pop, fit, *, F, CR, lo, hi, seed, gen, kind, o, R=None,
         _ptr(out["accept"], ctypes.c_int32), _ptr(out["draws"], ctypes.c_int32),
         nthreads)
     return out
+
+
+# jDE constants of Brest et al. (2006): F' = 0.1 + 0.9 u, tau_F = tau_CR = 0.1
+JDE_F_LO, JDE_F_SPAN, JDE_TAU_F, JDE_TAU_CR = 0.1, 0.9, 0.1, 0.1
+
+
+def jde_generation(pop, fit, F, CR, *, lo, hi, seed, gen, kind, o, R=None,
+                   F_lo=JDE_F_LO, F_span=JDE_F_SPAN, tau_F=JDE_TAU_F,
+                   tau_CR=JDE_TAU_CR, nthreads: int = 1, run0: int = 0):
+    """One synchronous jDE generation.  pop [runs,NP,D], fit/F/CR [runs,NP]
+    (FP64 holding FP32 control values).  F_lo, F_span, tau_F and tau_CR are
+    taken as the float32 values the GPU library stores.  Returns a dict with
+    pop_next, fit_next, F_next, CR_next, trial, ftrial, accept, Fp, CRp (the
+    F' and CR' each trial used)."""
+    pop, fit, o = _f64(pop), _f64(fit), _f64(o)
+    F, CR = _f64(F), _f64(CR)
+    runs, NP, D = pop.shape
+    Rm = _f64(R) if R is not None else np.zeros(1)
+    f32 = lambda v: float(np.float32(v))
+    out = dict(pop_next=np.empty_like(pop), fit_next=np.empty_like(fit),
+               F_next=np.empty_like(fit), CR_next=np.empty_like(fit),
+               trial=np.empty_like(pop), ftrial=np.empty_like(fit),
+               accept=np.empty((runs, NP), dtype=np.int32),
+               Fp=np.empty_like(fit), CRp=np.empty_like(fit))
+    dpt = ctypes.c_double
+    _load().oracle_jde_generation(
+        runs, run0, NP, D, f32(F_lo), f32(F_span), f32(tau_F), f32(tau_CR),
+        lo, hi, seed, gen, kind, _ptr(o, dpt), _ptr(Rm, dpt), _ptr(pop, dpt),
+        _ptr(fit, dpt), _ptr(F, dpt), _ptr(CR, dpt),
+        _ptr(out["pop_next"], dpt), _ptr(out["fit_next"], dpt),
+        _ptr(out["F_next"], dpt), _ptr(out["CR_next"], dpt),
+        _ptr(out["trial"], dpt), _ptr(out["ftrial"], dpt),
+        _ptr(out["accept"], ctypes.c_int32), _ptr(out["Fp"], dpt),
+        _ptr(out["CRp"], dpt), nthreads)
+    return out
+
+
+def jde_run(*, runs, NP, D, F0, CR0, lo, hi, seed, kind, o, R=None, G,
+            nthreads: int = 1, **jde):
+    """A whole jDE run (init + G generations), returns best_trace
+    [runs, G+1] and the final pop, fit, F, CR."""
+    pop = init_population(runs, NP, D, lo, hi, seed)
+    fit = objective_batch(kind, pop.reshape(-1, D), o, R,
+                          nthreads=nthreads).reshape(runs, NP)
+    F = np.full((runs, NP), float(np.float32(F0)))
+    CR = np.full((runs, NP), float(np.float32(CR0)))
+    best = np.empty((runs, G + 1))
+    best[:, 0] = fit.min(axis=1)
+    for g in range(G):
+        out = jde_generation(pop, fit, F, CR, lo=lo, hi=hi, seed=seed, gen=g,
+                             kind=kind, o=o, R=R, nthreads=nthreads, **jde)
+        pop, fit, F, CR = (out["pop_next"], out["fit_next"], out["F_next"],
+                           out["CR_next"])
+        best[:, g + 1] = fit.min(axis=1)
+    return dict(best_trace=best, pop=pop, fit=fit, F=F, CR=CR)
 
 
 def run(*, runs, NP, D, F, CR, lo, hi, seed, kind, o, R=None, G, target=1e-8,

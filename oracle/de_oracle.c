@@ -73,7 +73,7 @@ void oracle_philox_batch(const uint32_t* ctr, const uint32_t* key,
     oracle_philox4x32_10(ctr + 4 * t, key + 2 * t, out + 4 * t);
 }
 
-enum { OR_TAG_INIT = 1, OR_TAG_IDX = 2, OR_TAG_XOVER = 3 };
+enum { OR_TAG_INIT = 1, OR_TAG_IDX = 2, OR_TAG_XOVER = 3, OR_TAG_JDE = 4 };
 
 /* The four words drawn for (tag, run, gen, individual i, group q).
  * key = the 64-bit seed split into two words; counter = (q, i, gen,
@@ -257,6 +257,86 @@ void oracle_generation(int runs, int run0, int NP, int D, double F, double CR,
     if (ftrial) ftrial[t] = fu;
     if (accept) accept[t] = acc;
     if (draws) memcpy(draws + 4 * t, d, sizeof(d));
+    free(u);
+  }
+  (void)nthreads;
+}
+
+/* ---------------------------------------------------------------------- */
+/* jDE: control parameters adapted per individual (listed among the DE
+ * variants of Section 2; the GPU code cujDE of Section 8.2).  The rule and
+ * its constants are those of Brest, Greiner, Boskovic, Mernik & Zumer,
+ * "Self-adapting control parameters in differential evolution" (IEEE TEVC
+ * 2006), not of the paper.  Before building its trial, individual i draws
+ * four uniforms u1..u4 (one Philox block, tag 4, group 0) and takes
+ *     F'  = F_lo + u1 * F_span   if u2 < tau_F,   else F_i
+ *     CR' = u3                   if u4 < tau_CR,  else CR_i
+ * The trial uses F' and CR' in eqs. 2 and 3; when it replaces the target,
+ * F' and CR' replace F_i and CR_i, otherwise they are dropped.
+ * Readings: u = (w >> 8) * 2^-24 as in eq. 3; "u < tau" is decided as
+ * (w >> 8) < floor(tau * 2^24); control values are FP32 numbers: F' is
+ * F_lo + u1 F_span (computed exactly in FP64: u1 and F_span are 24-bit
+ * values and F_lo a float, so the sum needs fewer than 53 bits) rounded
+ * once to FP32, CR' = u3 is exact.  F and CR arrays are [runs][NP]; Fp/CRp
+ * (nullable) receive the F' and CR' each trial used.                      */
+static float or_round_float(double v) { return (float)v; }
+
+void oracle_jde_generation(int runs, int run0, int NP, int D, double F_lo,
+                           double F_span, double tau_F, double tau_CR,
+                           double lo, double hi, uint64_t seed, int64_t gen,
+                           int kind, const double* o, const double* R,
+                           const double* pop, const double* fit,
+                           const double* F, const double* CR,
+                           double* pop_next, double* fit_next,
+                           double* F_next, double* CR_next, double* trial,
+                           double* ftrial, int32_t* accept, double* Fp,
+                           double* CRp, int nthreads) {
+  const uint32_t tF = (uint32_t)floor(tau_F * 16777216.0);
+  const uint32_t tCR = (uint32_t)floor(tau_CR * 16777216.0);
+  int64_t total = (int64_t)runs * NP;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int64_t t = 0; t < total; ++t) {
+    int r = (int)(t / NP), i = (int)(t % NP);
+    const double* P = pop + (size_t)r * NP * D;
+    uint32_t w[4];
+    or_draw(seed, OR_TAG_JDE, (uint32_t)(run0 + r), (uint32_t)gen,
+            (uint32_t)i, 0u, w);
+    double Fi = F[t], CRi = CR[t];
+    if ((w[1] >> 8) < tF)
+      Fi = (double)or_round_float(F_lo + (double)(w[0] >> 8) *
+                                             (1.0 / 16777216.0) * F_span);
+    if ((w[3] >> 8) < tCR) CRi = (double)(w[2] >> 8) * (1.0 / 16777216.0);
+    int32_t d[4];
+    oracle_draw_indices(seed, run0 + r, gen, i, NP, D, d);
+    const double* x = P + (size_t)i * D;
+    const double* x1 = P + (size_t)d[0] * D;
+    const double* x2 = P + (size_t)d[1] * D;
+    const double* x3 = P + (size_t)d[2] * D;
+    double* u = (double*)malloc(sizeof(double) * (size_t)D);
+    for (int j = 0; j < D; ++j) {
+      if (oracle_take_mutant(seed, run0 + r, gen, i, j, d[3], CRi)) {
+        double v = x1[j] + Fi * (x2[j] - x3[j]);
+        if (v < lo) v = lo;
+        if (v > hi) v = hi;
+        u[j] = v;
+      } else {
+        u[j] = x[j];
+      }
+    }
+    double fu = oracle_objective(kind, D, u, o, R);
+    double fx = fit[t];
+    int acc = fu < fx;
+    memcpy(pop_next + (size_t)t * D, acc ? u : x, sizeof(double) * (size_t)D);
+    fit_next[t] = acc ? fu : fx;
+    F_next[t] = acc ? Fi : F[t];
+    CR_next[t] = acc ? CRi : CR[t];
+    if (trial) memcpy(trial + (size_t)t * D, u, sizeof(double) * (size_t)D);
+    if (ftrial) ftrial[t] = fu;
+    if (accept) accept[t] = acc;
+    if (Fp) Fp[t] = Fi;
+    if (CRp) CRp[t] = CRi;
     free(u);
   }
   (void)nthreads;

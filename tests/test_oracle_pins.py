@@ -463,3 +463,78 @@ def test_oracle_regression_fixture():
     assert int(res["hit_gen"][0]) == g["hit_gen"]
     assert [list(oracle.draw_indices(1, 0, 0, i, 64, 10))
             for i in range(4)] == gold["draws_seed1_np64_d10"]
+
+
+# --------------------------------------------------------------------------
+# jDE (control parameters adapted per individual; Section 2's list of DE
+# variants, Section 8.2).  The adaptation constants come from Brest et al.
+# (2006), not from the paper: parity of those constants is unpinned from the
+# paper; the rule's structure is pinned below.
+
+def _jde_setup(runs=2, NP=40, D=7, kind=1, seed=5):
+    o, R = instances.make_instance("rot_osc" if kind else "sphere", D, 1)
+    pop = oracle.init_population(runs, NP, D, LO, HI, seed)
+    fit = oracle.objective_batch(kind, pop.reshape(-1, D), o, R).reshape(
+        runs, NP)
+    F = np.full((runs, NP), 0.5)
+    CR = np.full((runs, NP), float(np.float32(0.9)))
+    return o, R, pop, fit, F, CR
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_jde_without_adaptation_is_plain_de(kind):
+    o, R, pop, fit, F, CR = _jde_setup(kind=kind)
+    a = oracle.jde_generation(pop, fit, F, CR, lo=LO, hi=HI, seed=5, gen=3,
+                              kind=kind, o=o, R=R, tau_F=0.0, tau_CR=0.0)
+    b = oracle.generation(pop, fit, F=0.5, CR=float(np.float32(0.9)), lo=LO,
+                          hi=HI, seed=5, gen=3, kind=kind, o=o, R=R)
+    for k in ("pop_next", "fit_next", "trial", "ftrial", "accept"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(a["F_next"], F)
+    np.testing.assert_array_equal(a["CR_next"], CR)
+
+
+def test_jde_new_values_are_uniform_on_their_ranges():
+    from scipy import stats
+    o, R, pop, fit, F, CR = _jde_setup(runs=8, NP=400, D=3)
+    out = oracle.jde_generation(pop, fit, F, CR, lo=LO, hi=HI, seed=5, gen=0,
+                                kind=1, o=o, R=R, tau_F=1.0, tau_CR=1.0)
+    Fp, CRp = out["Fp"].ravel(), out["CRp"].ravel()
+    assert Fp.min() >= 0.1 - 1e-7 and Fp.max() <= 1.0
+    np.testing.assert_array_equal(Fp, Fp.astype(np.float32))  # FP32 values
+    assert stats.kstest((Fp - 0.1) / 0.9, "uniform").pvalue > 1e-3
+    k = CRp * 2.0 ** 24
+    np.testing.assert_array_equal(k, np.floor(k))  # on the 2^-24 lattice
+    assert CRp.min() >= 0.0 and CRp.max() < 1.0
+    assert stats.kstest(CRp, "uniform").pvalue > 1e-3
+
+
+def test_jde_switch_rates_and_acceptance_rule():
+    o, R, pop, fit, F, CR = _jde_setup(runs=10, NP=500, D=3)
+    out = oracle.jde_generation(pop, fit, F, CR, lo=LO, hi=HI, seed=7, gen=2,
+                                kind=1, o=o, R=R)  # tau = 0.1 both
+    n = F.size
+    for new, old in ((out["Fp"], F), (out["CRp"], CR)):
+        rate = np.mean(new != old)
+        assert abs(rate - 0.1) < 4 * math.sqrt(0.09 / n)
+    acc = out["accept"].astype(bool)
+    np.testing.assert_array_equal(out["F_next"], np.where(acc, out["Fp"], F))
+    np.testing.assert_array_equal(out["CR_next"], np.where(acc, out["CRp"], CR))
+
+
+def test_jde_trial_uses_the_rows_own_parameters():
+    o, R, pop, fit, F, CR = _jde_setup(runs=2, NP=12, D=6, seed=9)
+    rng = np.random.default_rng(1)
+    F = rng.uniform(0.1, 1.0, F.shape).astype(np.float32).astype(np.float64)
+    CR = (rng.integers(0, 2 ** 24, CR.shape) / 2.0 ** 24)
+    out = oracle.jde_generation(pop, fit, F, CR, lo=LO, hi=HI, seed=9, gen=4,
+                                kind=1, o=o, R=R, tau_F=0.5, tau_CR=0.5)
+    for r in range(2):
+        for i in range(12):
+            r1, r2, r3, jr = oracle.draw_indices(9, r, 4, i, 12, 6)
+            Fi, CRi = out["Fp"][r, i], out["CRp"][r, i]
+            assert Fi == F[r, i] or 0.1 <= Fi <= 1.0
+            m = np.clip(pop[r, r1] + Fi * (pop[r, r2] - pop[r, r3]), LO, HI)
+            for j in range(6):
+                take = oracle.take_mutant(9, r, 4, i, j, jr, CRi)
+                assert out["trial"][r, i, j] == (m[j] if take else pop[r, i, j])
