@@ -178,6 +178,44 @@ DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
 DE_API de_status de_best(de_state* state, int32_t run, void* hip_stream,
                   float* x_host, double* f_host, int32_t* idx_host);
 
+/* jDE: DE/rand/1/bin whose F and CR are adapted per individual (listed
+ * among the DE variants of Section 2; the GPU code cujDE compared in
+ * Section 8.2).  The rule is that of Brest, Greiner, Boskovic, Mernik and
+ * Zumer (IEEE TEVC 2006): before building its trial, individual i takes
+ *     F' = F_lo + u1 F_span   with probability tau_F,   else its F,
+ *     CR' = u3                with probability tau_CR,  else its CR,
+ * with u on the 2^-24 lattice from Philox (tag 4, group 0 of (i, gen)); the
+ * trial uses F' and CR' in eqs. 2 and 3, and they replace the individual's
+ * values only if the trial replaces it.  Brest et al. use F_lo = 0.1,
+ * F_span = 0.9, tau_F = tau_CR = 0.1, and F = 0.5, CR = 0.9 at the start.
+ * Checks: F_lo >= 0, F_span > 0 (finite), tau in [0, 1].                   */
+typedef struct de_jde {
+  float F_lo;
+  float F_span;
+  float tau_F;
+  float tau_CR;
+} de_jde;
+
+/* As de_init_population, with jDE adaptation for every later generation;
+ * params->F and params->CR are every individual's starting values.  Same
+ * workspace size (the per-individual values are always reserved).        */
+DE_API de_status de_init_population_jde(const de_params* params,
+                                        const de_objective* objective,
+                                        const de_jde* jde,
+                                        const de_buffers* buffers,
+                                        void* hip_stream, de_state** out);
+
+/* jDE handles only (DE_E_STATE otherwise): copy the current generation's
+ * per-individual F and CR (runs * NP floats each, host arrays, individual
+ * (r, i) at r * NP + i) out of, or into, the workspace.  de_set_control
+ * checks F > 0 finite and CR in [0, 1] (DE_E_INVAL) and is the way to
+ * restore them with de_load_population (which keeps the current values).
+ * Both synchronise hip_stream.                                             */
+DE_API de_status de_get_control(de_state* state, void* hip_stream, float* F,
+                                float* CR);
+DE_API de_status de_set_control(de_state* state, void* hip_stream,
+                                const float* F, const float* CR);
+
 /* FP64 re-evaluation of every run's current best individual (the row the
  * FP32 best key points at): y = x - o and, for DE_OBJ_ROT_OSC, z = R y with R
  * as the FP32 matrix given at initialisation, are formed in FP64 and f is

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <unordered_set>
+#include <vector>
 
 #include "de.h"
 #include "de_internal.h"
@@ -25,7 +26,8 @@ constexpr uint64_t kMagic = 0x4445'6d69'3335'3578ull;
 constexpr int64_t kGenLimit = int64_t(1) << 32;  // counter field is 32-bit
 
 struct Layout {
-  size_t best, hit, acc, done, changed, opad, rop, rf32, f64, idx, total;
+  size_t best, hit, acc, done, changed, opad, rop, rf32, f64, idx, jp[2],
+      total;
 };
 
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
@@ -57,6 +59,9 @@ Layout layout_for(const de_params& p, int kind, int prec) {
   }
   L.f64 = take(8 * (size_t)p.runs);
   L.idx = take(4 * (size_t)p.runs);
+  // jDE control values (F, CR) per individual, generation g and g+1
+  L.jp[0] = take(8 * (size_t)p.runs * p.NP);
+  L.jp[1] = take(8 * (size_t)p.runs * p.NP);
   L.total = off;
   return L;
 }
@@ -75,6 +80,10 @@ struct de_state {
   uint32_t cr_threshold;
   float target;  // -inf outside de_evolve: no hit bookkeeping
   hipStream_t last_stream;
+  // jDE (de_init_population_jde): adaptation constants
+  int jde;
+  float jF_lo, jF_span;
+  uint32_t jtau_F, jtau_CR;
 };
 
 namespace {
@@ -152,6 +161,13 @@ GenArgs base_args(const de_state* s) {
   a.gen = (uint32_t)s->gen;
   a.key_lo = (uint32_t)s->p.seed;
   a.key_hi = (uint32_t)(s->p.seed >> 32);
+  a.jde = s->jde;
+  a.jp_cur = reinterpret_cast<const float2*>(s->work + s->L.jp[s->gen & 1]);
+  a.jp_next = reinterpret_cast<float2*>(s->work + s->L.jp[(s->gen + 1) & 1]);
+  a.jF_lo = s->jF_lo;
+  a.jF_span = s->jF_span;
+  a.jtau_F = s->jtau_F;
+  a.jtau_CR = s->jtau_CR;
   return a;
 }
 
@@ -243,13 +259,31 @@ DE_API de_status de_workspace_bytes(const de_params* params,
   return DE_OK;
 }
 
-DE_API de_status de_init_population(const de_params* params,
-                                    const de_objective* objective,
-                                    const de_buffers* buffers,
-                                    void* hip_stream, de_state** out) {
+}  // extern "C"
+
+namespace {
+
+// Adaptation constants of jDE: F' = F_lo + u F_span must stay a finite
+// positive weight; tau are probabilities.
+de_status check_jde(const de_jde* j) {
+  if (!j) return DE_E_INVAL;
+  if (!std::isfinite(j->F_lo) || !std::isfinite(j->F_span) ||
+      !(j->F_lo >= 0.f) || !(j->F_span > 0.f) ||
+      !std::isfinite(j->F_lo + j->F_span))
+    return DE_E_INVAL;
+  if (!(j->tau_F >= 0.f && j->tau_F <= 1.f) ||
+      !(j->tau_CR >= 0.f && j->tau_CR <= 1.f))
+    return DE_E_INVAL;
+  return DE_OK;
+}
+
+de_status init_common(const de_params* params, const de_objective* objective,
+                      const de_jde* jde, const de_buffers* buffers,
+                      void* hip_stream, de_state** out) {
   if (!out || !buffers) return DE_E_INVAL;
   de_status rc = check_problem(params, objective);
   if (rc != DE_OK) return rc;
+  if (jde && (rc = check_jde(jde)) != DE_OK) return rc;
   const de_params& p = *params;
   const int prec = objective->kind == de::kObjRotOsc ? objective->gemm_prec
                                                      : de::kPrecF32;
@@ -277,7 +311,8 @@ DE_API de_status de_init_population(const de_params* params,
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                               dev) != hipSuccess)
       return DE_E_DEVICE;
-    if (de::rot_lds_bytes_host(prec, dpad_for(p.D)) > (size_t)lds)
+    if (de::rot_lds_bytes_host(prec, dpad_for(p.D), jde != nullptr) >
+        (size_t)lds)
       return DE_E_UNSUPPORTED;
   }
 
@@ -299,6 +334,13 @@ DE_API de_status de_init_population(const de_params* params,
   s->cr_threshold = (uint32_t)std::floor((double)p.CR * 16777216.0);
   s->target = -std::numeric_limits<float>::infinity();
   s->last_stream = st;
+  s->jde = jde ? 1 : 0;
+  if (jde) {
+    s->jF_lo = jde->F_lo;
+    s->jF_span = jde->F_span;
+    s->jtau_F = (uint32_t)std::floor((double)jde->tau_F * 16777216.0);
+    s->jtau_CR = (uint32_t)std::floor((double)jde->tau_CR * 16777216.0);
+  }
 
   rc = from_hip(de::launch_prep(objective->o, objective->R, objective->ldr,
                                 p.D, s->dpad, s->kind, s->prec,
@@ -313,6 +355,10 @@ DE_API de_status de_init_population(const de_params* params,
     a.pop_next = s->pop[0];
     rc = from_hip(de::launch_init(a, st));
   }
+  if (rc == DE_OK && jde)
+    rc = from_hip(de::launch_fill_control(
+        reinterpret_cast<float2*>(s->work + L.jp[0]), p.runs * p.NP, p.F,
+        p.CR, st));
   if (rc == DE_OK) rc = eval_current_and_reset(s, st);
   if (rc != DE_OK) {
     s->magic = 0;
@@ -325,6 +371,74 @@ DE_API de_status de_init_population(const de_params* params,
   }
   *out = s;
   return DE_OK;
+}
+
+// (F, CR) of the current generation <-> host arrays.
+de_status control_io(de_state* state, void* hip_stream, float* F, float* CR,
+                     bool write) {
+  if (!live(state)) return DE_E_STATE;
+  if (!state->jde) return DE_E_STATE;
+  if (!F || !CR) return DE_E_INVAL;
+  const size_t n = (size_t)state->p.runs * state->p.NP;
+  if (write) {
+    for (size_t k = 0; k < n; ++k)
+      if (!(F[k] > 0.f) || !std::isfinite(F[k]) || !(CR[k] >= 0.f) ||
+          !(CR[k] <= 1.f))
+        return DE_E_INVAL;
+  }
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  float2* dev = reinterpret_cast<float2*>(state->work +
+                                          state->L.jp[state->gen & 1]);
+  std::vector<float2> h(n);
+  de_status rc = DE_OK;
+  if (write) {
+    for (size_t k = 0; k < n; ++k) h[k] = make_float2(F[k], CR[k]);
+    rc = from_hip(hipMemcpyAsync(dev, h.data(), 8 * n, hipMemcpyHostToDevice,
+                                 st));
+    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  } else {
+    rc = from_hip(hipMemcpyAsync(h.data(), dev, 8 * n, hipMemcpyDeviceToHost,
+                                 st));
+    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK)
+      for (size_t k = 0; k < n; ++k) {
+        F[k] = h[k].x;
+        CR[k] = h[k].y;
+      }
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+DE_API de_status de_init_population(const de_params* params,
+                                    const de_objective* objective,
+                                    const de_buffers* buffers,
+                                    void* hip_stream, de_state** out) {
+  return init_common(params, objective, nullptr, buffers, hip_stream, out);
+}
+
+DE_API de_status de_init_population_jde(const de_params* params,
+                                        const de_objective* objective,
+                                        const de_jde* jde,
+                                        const de_buffers* buffers,
+                                        void* hip_stream, de_state** out) {
+  if (!jde) return DE_E_INVAL;
+  return init_common(params, objective, jde, buffers, hip_stream, out);
+}
+
+DE_API de_status de_get_control(de_state* state, void* hip_stream, float* F,
+                                float* CR) {
+  return control_io(state, hip_stream, F, CR, false);
+}
+
+DE_API de_status de_set_control(de_state* state, void* hip_stream,
+                                const float* F, const float* CR) {
+  return control_io(state, hip_stream, const_cast<float*>(F),
+                    const_cast<float*>(CR), true);
 }
 
 DE_API de_status de_generation(de_state* state, int32_t n_gens,
@@ -487,6 +601,14 @@ DE_API de_status de_load_population(de_state* state, int64_t gen,
   (void)hipGetLastError();
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   state->last_stream = st;
+  if (state->jde && ((gen ^ state->gen) & 1)) {
+    // jDE: the control values move with the generation's parity
+    const de_status rc = from_hip(hipMemcpyAsync(
+        state->work + state->L.jp[gen & 1],
+        state->work + state->L.jp[state->gen & 1],
+        8 * (size_t)state->p.runs * state->p.NP, hipMemcpyDeviceToDevice, st));
+    if (rc != DE_OK) return rc;
+  }
   state->gen = gen;
   return eval_current_and_reset(state, st);
 }

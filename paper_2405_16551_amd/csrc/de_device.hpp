@@ -15,7 +15,7 @@
 
 namespace de {
 
-enum : uint32_t { kTagInit = 1u, kTagIdx = 2u, kTagXover = 3u };
+enum : uint32_t { kTagInit = 1u, kTagIdx = 2u, kTagXover = 3u, kTagJde = 4u };
 
 // Philox4x32-10 multipliers and Weyl key increments (Salmon et al., Sec. 4).
 constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
@@ -120,6 +120,32 @@ __host__ __device__ __forceinline__ float mutant_coord(float x1, float x2, float
   v = v < lo ? lo : v;
   v = v > hi ? hi : v;
   return v;
+}
+
+// jDE control values of individual i for this generation (self-adaptation
+// of Brest et al., 2006): one Philox block (tag 4, group 0) gives u1..u4 on
+// the 2^-24 lattice; F' = F_lo + u1 F_span (one fused rounding) if
+// u2 < tau_F, else the stored F; CR' = u3 if u4 < tau_CR, else the stored
+// CR.  tau thresholds are floor(tau 2^24), compared in integers.
+struct Control {
+  float F, CR;
+};
+
+__host__ __device__ __forceinline__ Control jde_control(
+    uint32_t run, uint32_t gen, int i, uint32_t key_lo, uint32_t key_hi,
+    float F_lo, float F_span, uint32_t tau_F, uint32_t tau_CR, Control cur) {
+  const Words4 w = draw_block(kTagJde, run, gen, (uint32_t)i, 0u, key_lo,
+                              key_hi);
+  Control c = cur;
+  if ((w.w[1] >> 8) < tau_F)
+    c.F = fmaf((float)(w.w[0] >> 8) * 0x1.0p-24f, F_span, F_lo);
+  if ((w.w[3] >> 8) < tau_CR) c.CR = (float)(w.w[2] >> 8) * 0x1.0p-24f;
+  return c;
+}
+
+// floor(CR 2^24) for a float CR in [0, 1] (the scaling is exact).
+__host__ __device__ __forceinline__ uint32_t cr_threshold_of(float CR) {
+  return (uint32_t)(CR * 16777216.0f);
 }
 
 // Totally ordered 64-bit key: order-preserving image of the float in the high

@@ -29,15 +29,24 @@ struct GenArgs {
   float F, lo, hi, target;
   uint32_t cr_threshold, gen, key_lo, key_hi;
   uint32_t run_base;  // rotated kernels: draw-counter run = run_base + run
+  // jDE (jde != 0): per-individual (F, CR) of generation g and g+1, and the
+  // adaptation constants (tau as floor(tau 2^24))
+  int jde;
+  const float2* jp_cur;
+  float2* jp_next;
+  float jF_lo, jF_span;
+  uint32_t jtau_F, jtau_CR;
 };
 
-size_t rot_lds_bytes_host(int prec, int dpad);
+size_t rot_lds_bytes_host(int prec, int dpad, bool jde = false);
 bool sep_supported(int D);
 
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,
                              hipStream_t s);
 hipError_t launch_eval(const GenArgs& a, int kind, int prec, hipStream_t s);
 hipError_t launch_init(const GenArgs& a, hipStream_t s);
+hipError_t launch_fill_control(float2* jp, int n, float F, float CR,
+                               hipStream_t s);
 hipError_t launch_prep(const float* o, const float* R, int ldr, int D,
                        int dpad, int kind, int prec, float* o_pad, void* rop,
                        hipStream_t s);

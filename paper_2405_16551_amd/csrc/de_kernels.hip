@@ -26,7 +26,7 @@ namespace de {
 
 // ---------------------------------------------------------------------------
 // Separable objective.  EVAL: f of rows pop_cur[0..nrows) into fit_next.
-template <int LPI, int ITER, bool EVAL>
+template <int LPI, int ITER, bool EVAL, bool JDE>
 __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
   constexpr int IPB = 256 / LPI;
   const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
@@ -43,6 +43,16 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
 
   Donors d{0, 0, 0, 0};
   const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
+  float F = a.F;
+  uint32_t crt = a.cr_threshold;
+  Control ctl{0.f, 0.f};
+  if (JDE && !EVAL) {
+    const float2 c = a.jp_cur[g];
+    ctl = jde_control((uint32_t)run, a.gen, i, a.key_lo, a.key_hi, a.jF_lo,
+                      a.jF_span, a.jtau_F, a.jtau_CR, Control{c.x, c.y});
+    F = ctl.F;
+    crt = cr_threshold_of(ctl.CR);
+  }
   if (!EVAL) {
     d = pick_donors((uint32_t)run, a.gen, i, a.NP, a.D, a.key_lo, a.key_hi);
     const float* base = a.pop_cur + (size_t)run * a.NP * a.ldx;
@@ -74,9 +84,9 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const bool tk = (j0 + b < a.D) &&
-                        take_mutant(w.w[b], j0 + b, d.jrand, a.cr_threshold);
+                        take_mutant(w.w[b], j0 + b, d.jrand, crt);
         const float mv = mutant_coord(get(v1[it], b), get(v2[it], b),
-                                      get(v3[it], b), a.F, a.lo, a.hi);
+                                      get(v3[it], b), F, a.lo, a.hi);
         set(uv[it], b, tk ? mv : get(xv[it], b));
       }
     }
@@ -106,11 +116,14 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
   if (ln == 0) {
     a.fit_next[g] = accept ? f : fx;
     a.changed[g] = accept ? 1 : 0;
+    if constexpr (JDE) {
+      a.jp_next[g] = accept ? make_float2(ctl.F, ctl.CR) : a.jp_cur[g];
+    }
     if (accept) record_accept(a, run, i, f);
   }
 }
 
-template <class P, int BM, int NT, bool EVAL>
+template <class P, int BM, int NT, bool EVAL, bool JDE>
 __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
   const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
   int run = 0, row0 = 0, nvalid = 0;
@@ -123,7 +136,14 @@ __global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
     row0 = (lb - run * tiles) * BM;
     nvalid = min(BM, a.NP - row0);
   }
-  rot_tile<P, BM, NT, EVAL>(a, run, row0, nvalid);
+  rot_tile<P, BM, NT, EVAL, JDE>(a, run, row0, nvalid);
+}
+
+// jDE: every individual starts from the same (F, CR).
+__global__ __launch_bounds__(256) void k_fill_control(float2* jp, int n,
+                                                      float F, float CR) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < n; t += gridDim.x * 256)
+    jp[t] = make_float2(F, CR);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,37 +363,43 @@ int grid_for(size_t work, int per_block) {
   return (int)b;
 }
 
-template <int LPI, int ITER, bool EVAL>
+template <int LPI, int ITER, bool EVAL, bool JDE>
 hipError_t launch_sep_t(const GenArgs& a, hipStream_t s) {
   constexpr int IPB = 256 / LPI;
   const int blocks = (a.nrows + IPB - 1) / IPB;
-  hipLaunchKernelGGL((k_sep<LPI, ITER, EVAL>), dim3(blocks), dim3(256), 0, s,
-                     a);
+  hipLaunchKernelGGL((k_sep<LPI, ITER, EVAL, JDE>), dim3(blocks), dim3(256),
+                     0, s, a);
   return hipGetLastError();
+}
+
+template <bool EVAL, bool JDE>
+hipError_t launch_sep_j(const GenArgs& a, hipStream_t s) {
+  const int nq = (a.D + 3) / 4;
+  if (nq <= 4) return launch_sep_t<4, 1, EVAL, JDE>(a, s);
+  if (nq <= 8) return launch_sep_t<8, 1, EVAL, JDE>(a, s);
+  if (nq <= 16) return launch_sep_t<16, 1, EVAL, JDE>(a, s);
+  if (nq <= 32) return launch_sep_t<32, 1, EVAL, JDE>(a, s);
+  if (nq <= 64) return launch_sep_t<64, 1, EVAL, JDE>(a, s);
+  if (nq <= 128) return launch_sep_t<64, 2, EVAL, JDE>(a, s);
+  if (nq <= 256) return launch_sep_t<64, 4, EVAL, JDE>(a, s);
+  if (nq <= 512) return launch_sep_t<64, 8, EVAL, JDE>(a, s);
+  if (nq <= 1024) return launch_sep_t<64, 16, EVAL, JDE>(a, s);
+  return hipErrorInvalidValue;
 }
 
 template <bool EVAL>
 hipError_t launch_sep_e(const GenArgs& a, hipStream_t s) {
-  const int nq = (a.D + 3) / 4;
-  if (nq <= 4) return launch_sep_t<4, 1, EVAL>(a, s);
-  if (nq <= 8) return launch_sep_t<8, 1, EVAL>(a, s);
-  if (nq <= 16) return launch_sep_t<16, 1, EVAL>(a, s);
-  if (nq <= 32) return launch_sep_t<32, 1, EVAL>(a, s);
-  if (nq <= 64) return launch_sep_t<64, 1, EVAL>(a, s);
-  if (nq <= 128) return launch_sep_t<64, 2, EVAL>(a, s);
-  if (nq <= 256) return launch_sep_t<64, 4, EVAL>(a, s);
-  if (nq <= 512) return launch_sep_t<64, 8, EVAL>(a, s);
-  if (nq <= 1024) return launch_sep_t<64, 16, EVAL>(a, s);
-  return hipErrorInvalidValue;
+  if (!EVAL && a.jde) return launch_sep_j<false, true>(a, s);
+  return launch_sep_j<EVAL, false>(a, s);
 }
 
-template <class P, int BM, int NT, bool EVAL>
+template <class P, int BM, int NT, bool EVAL, bool JDE = false>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
-  const size_t lds = rot_lds_bytes<P, BM, NT>(a.dpad);
+  const size_t lds = rot_lds_bytes<P, BM, NT, JDE>(a.dpad);
   static bool attr_done = false;
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL>),
+        reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL, JDE>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
     if (e != hipSuccess) return e;
     attr_done = true;
@@ -384,13 +410,18 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   } else {
     blocks = a.runs * ((a.NP + BM - 1) / BM);
   }
-  hipLaunchKernelGGL((k_rot<P, BM, NT, EVAL>), dim3(blocks), dim3(NT), lds, s,
-                     a);
+  hipLaunchKernelGGL((k_rot<P, BM, NT, EVAL, JDE>), dim3(blocks), dim3(NT),
+                     lds, s, a);
   return hipGetLastError();
 }
 
 template <bool EVAL>
 hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
+  if (!EVAL && a.jde) {
+    if (prec != kPrecBF16)
+      return launch_rot_t<PrecF32, 32, 512, false, true>(a, s);
+    return launch_rot_t<PrecBF16, 64, 512, false, true>(a, s);
+  }
   if (prec != kPrecBF16) return launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
   return launch_rot_t<PrecBF16, 64, 512, EVAL>(a, s);
 }
@@ -399,7 +430,10 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
 
 // LDS bytes of the rotated kernel: BF16 tiles of 64 rows, FP32 tiles of 32
 // rows, both 512 threads.
-size_t rot_lds_bytes_host(int prec, int dpad) {
+size_t rot_lds_bytes_host(int prec, int dpad, bool jde) {
+  if (jde)
+    return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, 512, true>(dpad)
+                             : rot_lds_bytes<PrecF32, 32, 512, true>(dpad);
   return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, 512>(dpad)
                            : rot_lds_bytes<PrecF32, 32, 512>(dpad);
 }
@@ -420,6 +454,13 @@ hipError_t launch_eval(const GenArgs& a, int kind, int prec, hipStream_t s) {
 hipError_t launch_init(const GenArgs& a, hipStream_t s) {
   const size_t work = (size_t)a.nrows * ((a.D + 3) / 4);
   hipLaunchKernelGGL(k_init, dim3(grid_for(work, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_control(float2* jp, int n, float F, float CR,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_control, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                     jp, n, F, CR);
   return hipGetLastError();
 }
 

@@ -66,13 +66,14 @@ struct PrecF32 {
   static constexpr int kPad = 4;
 };
 
-template <class P, int BM, int NT>
+template <class P, int BM, int NT, bool JDE = false>
 __host__ __device__ constexpr size_t rot_lds_bytes(int dpad) {
   const int tq = (dpad / 4 + 63) / 64;
   return (size_t)BM * (dpad + P::kPad) * sizeof(typename P::T)  // A tile
          + (size_t)BM * tq * 4 * sizeof(unsigned long long)     // planes
          + (size_t)BM * 4 * sizeof(int)                         // donors
-         + (size_t)(NT / 64) * BM * sizeof(float);              // partials
+         + (size_t)(NT / 64) * BM * sizeof(float)               // partials
+         + (JDE ? (size_t)BM * sizeof(Control) : 0);            // F', CR'
 }
 
 // Position of coordinate k inside an LDS row.  BF16: natural order.  FP32:
@@ -170,7 +171,7 @@ __device__ __forceinline__ void f32_step(const float* ar, int k8, float4 b0,
 // flattened row range).  Ends with every LDS access of the tile complete
 // only for the calling thread: a caller that runs another tile in the same
 // workgroup synchronises first.
-template <class P, int BM, int NT, bool EVAL>
+template <class P, int BM, int NT, bool EVAL, bool JDE = false>
 __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
                                          int nvalid) {
   using T = typename P::T;
@@ -187,6 +188,8 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       smem + (size_t)BM * stride * sizeof(T));
   int* donors = reinterpret_cast<int*>(planes + (size_t)BM * tq * 4);
   float* fpart = reinterpret_cast<float*>(donors + BM * 4);
+  // jDE: the F' and CR' of every row of the tile
+  Control* ctl = reinterpret_cast<Control*>(fpart + kRotWaves * BM);
 
   const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
   const uint32_t rng_run = a.run_base + (uint32_t)run;
@@ -201,6 +204,12 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       donors[rl * 4 + 1] = d.r2;
       donors[rl * 4 + 2] = d.r3;
       donors[rl * 4 + 3] = d.jrand;
+      if constexpr (JDE) {
+        const float2 c = a.jp_cur[(size_t)run * a.NP + row0 + rl];
+        ctl[rl] = jde_control(rng_run, a.gen, row0 + rl, a.key_lo, a.key_hi,
+                              a.jF_lo, a.jF_span, a.jtau_F, a.jtau_CR,
+                              Control{c.x, c.y});
+      }
     }
     __syncthreads();
   }
@@ -257,6 +266,13 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
           const int rl = wave + kRotWaves * (k + h);
           const int i = row0 + rl;
           const int jrand = EVAL ? 0 : donors[rl * 4 + 3];
+          float Fr = a.F;
+          uint32_t crt = a.cr_threshold;
+          if constexpr (JDE && !EVAL) {
+            const Control c = ctl[rl];
+            Fr = c.F;
+            crt = cr_threshold_of(c.CR);
+          }
           T* arow = At + (size_t)rl * stride;
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -273,10 +289,10 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
               for (int b = 0; b < 4; ++b) {
                 const bool tk =
                     (j0 + b < a.D) &&
-                    take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold);
+                    take_mutant(w.w[b], j0 + b, jrand, crt);
                 const float mv =
                     mutant_coord(get(c[h].v1[u], b), get(c[h].v2[u], b),
-                                 get(c[h].v3[u], b), a.F, a.lo, a.hi);
+                                 get(c[h].v3[u], b), Fr, a.lo, a.hi);
                 set(uu, b, tk ? mv : get(c[h].xv[u], b));
                 bits |= (tk ? 1u : 0u) << b;
               }
@@ -447,6 +463,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     const float fx = a.fit_cur[g];
     const bool accept = f < fx;
     const bool refresh = !accept && a.changed[g] != 0;
+    const float Fr = JDE ? ctl[rl].F : a.F;
     if (accept || refresh) {
       const float* xrow = base + (size_t)i * a.ldx;
       float* nrow = a.pop_next + g * a.ldx;
@@ -477,7 +494,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
             for (int b = 0; b < 4; ++b) {
               const unsigned long long m = planes[((size_t)rl * tq + t) * 4 + b];
               const float mv = mutant_coord(get(v1[u], b), get(v2[u], b),
-                                            get(v3[u], b), a.F, a.lo, a.hi);
+                                            get(v3[u], b), Fr, a.lo, a.hi);
               set(out, b, ((m >> lane) & 1ull) ? mv : get(xv[u], b));
             }
           }
@@ -488,6 +505,11 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     if (lane == 0) {
       a.fit_next[g] = accept ? f : fx;
       a.changed[g] = accept ? 1 : 0;
+      if constexpr (JDE) {
+        // the trial's F', CR' survive only with the trial
+        a.jp_next[g] = accept ? make_float2(ctl[rl].F, ctl[rl].CR)
+                              : a.jp_cur[g];
+      }
       if (accept) record_accept(a, run, i, f);
     }
   }

@@ -44,6 +44,15 @@ class de_buffers(ctypes.Structure):
                 ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
 
 
+class de_jde(ctypes.Structure):
+    _fields_ = [("F_lo", ctypes.c_float), ("F_span", ctypes.c_float),
+                ("tau_F", ctypes.c_float), ("tau_CR", ctypes.c_float)]
+
+
+# Brest et al. (2006): F' = 0.1 + 0.9 u, tau_F = tau_CR = 0.1
+JDE_BREST = dict(F_lo=0.1, F_span=0.9, tau_F=0.1, tau_CR=0.1)
+
+
 class de_run_spec(ctypes.Structure):
     _fields_ = [("NP", ctypes.c_int32), ("D", ctypes.c_int32),
                 ("F", ctypes.c_float), ("CR", ctypes.c_float)]
@@ -72,6 +81,7 @@ EXPORTS = ("de_abi_version", "de_strerror", "de_workspace_bytes",
            "de_init_population", "de_generation", "de_evolve", "de_best",
            "de_best_f64", "de_get_generation", "de_read_stats", "de_load_population",
            "de_eval", "de_debug_draws", "de_destroy",
+           "de_init_population_jde", "de_get_control", "de_set_control",
            # include/de_batch.h
            "de_batch_layout", "de_batch_create", "de_batch_plan",
            "de_batch_generation", "de_batch_read", "de_batch_get_generation",
@@ -97,6 +107,15 @@ def _load():
     lib.de_init_population.restype = st
     lib.de_init_population.argtypes = [P(de_params), P(de_objective),
                                        P(de_buffers), vp, P(vp)]
+    lib.de_init_population_jde.restype = st
+    lib.de_init_population_jde.argtypes = [P(de_params), P(de_objective),
+                                           P(de_jde), P(de_buffers), vp,
+                                           P(vp)]
+    fp = P(ctypes.c_float)
+    lib.de_get_control.restype = st
+    lib.de_get_control.argtypes = [vp, vp, fp, fp]
+    lib.de_set_control.restype = st
+    lib.de_set_control.argtypes = [vp, vp, fp, fp]
     lib.de_generation.restype = st
     lib.de_generation.argtypes = [vp, i32, vp]
     lib.de_evolve.restype = st
@@ -179,6 +198,30 @@ def de_init_population(params, objective, buffers, stream) -> ctypes.c_void_p:
                                    ctypes.byref(buffers), stream,
                                    ctypes.byref(h)), "de_init_population")
     return h
+
+
+def de_init_population_jde(params, objective, jde, buffers, stream):
+    h = ctypes.c_void_p()
+    _check(_lib.de_init_population_jde(ctypes.byref(params),
+                                       ctypes.byref(objective),
+                                       ctypes.byref(jde),
+                                       ctypes.byref(buffers), stream,
+                                       ctypes.byref(h)),
+           "de_init_population_jde")
+    return h
+
+
+def de_get_control(handle, stream, n: int):
+    F = (ctypes.c_float * n)()
+    CR = (ctypes.c_float * n)()
+    _check(_lib.de_get_control(handle, stream, F, CR), "de_get_control")
+    return list(F), list(CR)
+
+
+def de_set_control(handle, stream, F, CR):
+    n = len(F)
+    _check(_lib.de_set_control(handle, stream, (ctypes.c_float * n)(*F),
+                               (ctypes.c_float * n)(*CR)), "de_set_control")
 
 
 def de_generation(handle, n_gens: int, stream):
@@ -308,11 +351,14 @@ class DifferentialEvolution:
 
     ``o`` (D floats) and, for 'rot_osc', ``R`` (D x D, row-major, z = R y)
     may be NumPy arrays or tensors; they are copied to the device.
+    ``jde``: None (plain DE/rand/1/bin), True (Brest et al. constants) or a
+    dict with F_lo, F_span, tau_F, tau_CR; F and CR are then the starting
+    values of every individual.
     """
 
     def __init__(self, *, runs, NP, D, F, CR, lo=-100.0, hi=100.0, seed=1,
                  kind="sphere", o, R=None, gemm_prec="bf16", ldx=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, jde=None):
         import torch
         self.torch = torch
         self.runs, self.NP, self.D = int(runs), int(NP), int(D)
@@ -342,8 +388,16 @@ class DifferentialEvolution:
             (ctypes.c_void_p * 2)(self.pop[0].data_ptr(), self.pop[1].data_ptr()),
             (ctypes.c_void_p * 2)(self.fit[0].data_ptr(), self.fit[1].data_ptr()),
             self.ldx, 0, wptr, wbytes)
-        self.handle = de_init_population(self.params, self.objective,
-                                         self.buffers, self._s())
+        if jde:
+            j = dict(JDE_BREST) if jde is True else dict(jde)
+            self.jde = de_jde(j["F_lo"], j["F_span"], j["tau_F"], j["tau_CR"])
+            self.handle = de_init_population_jde(self.params, self.objective,
+                                                 self.jde, self.buffers,
+                                                 self._s())
+        else:
+            self.jde = None
+            self.handle = de_init_population(self.params, self.objective,
+                                             self.buffers, self._s())
 
     def _s(self):
         return self.stream.cuda_stream
@@ -379,6 +433,19 @@ class DifferentialEvolution:
 
     def stats(self):
         return de_read_stats(self.handle, self._s(), self.runs)
+
+    def control(self):
+        """jDE: (F, CR) of the current generation as float32 [runs, NP]."""
+        import numpy as np
+        F, CR = de_get_control(self.handle, self._s(), self.runs * self.NP)
+        return (np.asarray(F, np.float32).reshape(self.runs, self.NP),
+                np.asarray(CR, np.float32).reshape(self.runs, self.NP))
+
+    def set_control(self, F, CR):
+        import numpy as np
+        de_set_control(self.handle, self._s(),
+                       np.asarray(F, np.float32).ravel().tolist(),
+                       np.asarray(CR, np.float32).ravel().tolist())
 
     def population(self, gen=None):
         """View [runs, NP, D] of pop[gen & 1] (current generation by default)."""

@@ -13,12 +13,12 @@ FP32_RTOL = 1e-5  # one-generation fitness tolerance in FP32
 
 
 def make_de(*, runs, NP, D, F=0.5, CR=0.9, seed=1, kind="sphere",
-            gemm_prec="fp32", obj_seed=1, ldx=None):
+            gemm_prec="fp32", obj_seed=1, ldx=None, jde=None):
     from paper_2405_16551_amd.de import DifferentialEvolution
     o, R = instances.make_instance(kind, D, obj_seed)
     de = DifferentialEvolution(runs=runs, NP=NP, D=D, F=F, CR=CR, lo=LO,
                                hi=HI, seed=seed, kind=kind, o=o, R=R,
-                               gemm_prec=gemm_prec, ldx=ldx)
+                               gemm_prec=gemm_prec, ldx=ldx, jde=jde)
     return de, o, R
 
 

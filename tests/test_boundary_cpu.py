@@ -31,7 +31,7 @@ def test_every_header_is_covered():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 21
+    assert len(names) == 24
     assert set(names) == set(d.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", d.LIB_PATH],
                          capture_output=True, text=True, check=True).stdout
@@ -187,3 +187,30 @@ def test_product_never_touches_the_oracle():
             src = open(os.path.join(ROOT, "oracle", fn)).read()
             assert "paper_2405_16551_amd" not in src, fn
             assert "de_device" not in src and "libde" not in src, fn
+
+
+@pytest.mark.parametrize("jkw", [
+    dict(F_span=0.0), dict(F_span=-0.5), dict(F_lo=-0.1), dict(F_lo=math.nan),
+    dict(F_span=math.inf), dict(tau_F=-0.1), dict(tau_F=1.5),
+    dict(tau_CR=math.nan), dict(tau_CR=2.0)])
+def test_invalid_jde_constants_rejected(jkw):
+    base = dict(d.JDE_BREST)
+    base.update(jkw)
+    j = d.de_jde(base["F_lo"], base["F_span"], base["tau_F"], base["tau_CR"])
+    h = ctypes.c_void_p()
+    bufs = d.de_buffers((ctypes.c_void_p * 2)(256, 512),
+                        (ctypes.c_void_p * 2)(768, 1024), 1000, 0, 1 << 20,
+                        1 << 40)
+    st = d._lib.de_init_population_jde(ctypes.byref(P()), ctypes.byref(O()),
+                                       ctypes.byref(j), ctypes.byref(bufs),
+                                       None, ctypes.byref(h))
+    assert st == d.DE_E_INVAL
+    assert d._lib.de_init_population_jde(ctypes.byref(P()), ctypes.byref(O()),
+                                         None, ctypes.byref(bufs), None,
+                                         ctypes.byref(h)) == d.DE_E_INVAL
+
+
+def test_control_calls_need_a_jde_handle():
+    f = (ctypes.c_float * 4)()
+    assert d._lib.de_get_control(None, None, f, f) == d.DE_E_STATE
+    assert d._lib.de_set_control(None, None, f, f) == d.DE_E_STATE
