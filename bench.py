@@ -45,6 +45,11 @@ WORKLOADS = {
     "rot100_r64": dict(runs=64, NP=256, D=100, kind="rot_osc",
                        gemm_prec="fp32"),
     "sphere10": dict(runs=1, NP=64, D=10, kind="sphere", gemm_prec="fp32"),
+    # jDE (per-individual F, CR; Brest et al. constants), same sizes
+    "rot1000_bf16_jde": dict(runs=16, NP=1024, D=1000, kind="rot_osc",
+                             gemm_prec="bf16", jde=True),
+    "sphere1000_jde": dict(runs=16, NP=1024, D=1000, kind="sphere",
+                           gemm_prec="fp32", jde=True),
 }
 
 
@@ -52,6 +57,10 @@ def describe(name):
     w = WORKLOADS[name]
     obj = ("shifted sphere" if w["kind"] == "sphere" else
            f"rotated oscillating, {w['gemm_prec']} rotation product")
+    if w.get("jde"):
+        return (f"jDE (DE/rand/1/bin, per-individual F and CR adapted as in "
+                f"Brest et al. 2006), {w['runs']} runs x NP={w['NP']}, "
+                f"D={w['D']}, {obj}, F=0.5, CR=0.9 at the start")
     return (f"DE/rand/1/bin, {w['runs']} runs x NP={w['NP']}, D={w['D']}, "
             f"{obj}, F=0.5, CR=0.9")
 
@@ -104,7 +113,8 @@ def time_workload(name, steps, warmup, seed=1):
     o, R = instances.make_instance(w["kind"], w["D"], 1)
     de = DifferentialEvolution(runs=w["runs"], NP=w["NP"], D=w["D"], F=0.5,
                                CR=0.9, seed=seed, kind=w["kind"], o=o, R=R,
-                               gemm_prec=w["gemm_prec"])
+                               gemm_prec=w["gemm_prec"],
+                               jde=w.get("jde"))
     stream = de.stream
     de.generation(warmup)
     torch.cuda.synchronize()
@@ -358,6 +368,12 @@ def main():
             "gens_per_s": round(c["gens_per_s"], 2),
             "kernel_ms_per_step": round(c["kernel_ms"], 5),
             "accept_rate": c["accept_rate"], "roofline": c["roofline"]}
+        jname = "rot1000_bf16_jde" if w["kind"] == "rot_osc" else "sphere1000_jde"
+        j = time_workload(jname, max(50, args.steps // 4), args.warmup)
+        line["jde"] = {
+            "workload": describe(jname), "evals_per_s": round(j["evals_per_s"], 1),
+            "kernel_ms_per_step": round(j["kernel_ms"], 5),
+            "accept_rate": j["accept_rate"], "roofline": j["roofline"]}
         line["batched"] = time_batch(max(64, args.steps // 4), args.warmup)
         line["time_to_target"] = time_to_target()
         line["copy_ceiling"] = copy_ceiling()
