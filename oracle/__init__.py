@@ -74,6 +74,23 @@ def _load():
         c_int, c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl,
         c_u64, c_i64, c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
         i32p, dp, dp, c_int]
+    lib.oracle_composition_batch.argtypes = [c_int, c_int, c_i64, dp, dp, dp,
+                                             dp, c_dbl, dp, c_int]
+    lib.oracle_mlp_size.argtypes = [c_int, c_int]
+    lib.oracle_mlp_size.restype = c_i64
+    lib.oracle_mlp_forward.argtypes = [c_int, c_int, dp, c_dbl, c_dbl, c_i64,
+                                       dp, dp]
+    lib.oracle_mlp_grad.argtypes = [c_int, c_int, dp, c_dbl, c_dbl, c_int, dp,
+                                    dp, dp]
+    lib.oracle_mlp_grad.restype = c_dbl
+    lib.oracle_mlp_adam_step.argtypes = [c_int, c_int, dp, dp, dp, c_i64,
+                                         c_dbl, c_dbl, c_dbl, c_dbl, c_dbl,
+                                         c_dbl, c_int, dp, dp]
+    lib.oracle_mlp_adam_step.restype = c_dbl
+    lib.oracle_sur_generation.argtypes = [
+        c_int, c_int, c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64,
+        c_i64, c_int, c_int, dp, c_int, dp, dp, dp, c_dbl, dp, dp, dp, dp, dp,
+        dp, i32p, dp, i32p, c_int]
     lib.oracle_run.argtypes = [
         c_int, c_int, c_int, c_dbl, c_dbl, c_dbl, c_dbl, c_u64, c_int, dp, dp,
         c_i64, c_dbl, dp, i64p, i64p, dp, dp, c_int]
@@ -262,3 +279,82 @@ def run(*, runs, NP, D, F, CR, lo, hi, seed, kind, o, R=None, G, target=1e-8,
     if rc != 0:
         raise MemoryError("oracle_run: allocation failed")
     return dict(best_trace=best, hit_gen=hit, accepted=acc, pop=pop, fit=fit)
+
+
+# ---------------------------------------------------------------------------
+# Composition objective, surrogate MLP and the surrogate-assisted generation.
+
+def composition_batch(X, O, R, bias, sigma, nthreads: int = 1):
+    """f of rows X [n, D] for the composition of len(bias) components:
+    shifts O [n_c, D], rotations R [n_c, D, D]."""
+    X = _f64(X)
+    O, R, bias = _f64(O), _f64(R), _f64(bias)
+    n_c, D = O.shape
+    assert n_c <= 64
+    X2 = X.reshape(-1, D)
+    f = np.empty(X2.shape[0], dtype=np.float64)
+    dpt = ctypes.c_double
+    _load().oracle_composition_batch(D, n_c, X2.shape[0], _ptr(X2, dpt),
+                                     _ptr(O, dpt), _ptr(R, dpt),
+                                     _ptr(bias, dpt), float(sigma),
+                                     _ptr(f, dpt), nthreads)
+    return f.reshape(X.shape[:-1])
+
+
+def mlp_size(D: int, H: int) -> int:
+    return int(_load().oracle_mlp_size(D, H))
+
+
+def mlp_forward(theta, X, *, D, H, lo, hi):
+    theta, X = _f64(theta), _f64(X).reshape(-1, D)
+    y = np.empty(X.shape[0], dtype=np.float64)
+    dpt = ctypes.c_double
+    _load().oracle_mlp_forward(D, H, _ptr(theta, dpt), lo, hi, X.shape[0],
+                               _ptr(X, dpt), _ptr(y, dpt))
+    return y
+
+
+def mlp_grad(theta, X, T, *, D, H, lo, hi):
+    theta, X, T = _f64(theta), _f64(X).reshape(-1, D), _f64(T)
+    g = np.empty_like(theta)
+    dpt = ctypes.c_double
+    loss = _load().oracle_mlp_grad(D, H, _ptr(theta, dpt), lo, hi, X.shape[0],
+                                   _ptr(X, dpt), _ptr(T, dpt), _ptr(g, dpt))
+    return loss, g
+
+
+def mlp_adam_step(theta, m, v, t, X, T, *, D, H, lo, hi, lr, beta1, beta2,
+                  eps):
+    """Returns (loss, theta', m', v') after one Adam step (t >= 1)."""
+    theta, m, v = _f64(theta).copy(), _f64(m).copy(), _f64(v).copy()
+    X, T = _f64(X).reshape(-1, D), _f64(T)
+    dpt = ctypes.c_double
+    loss = _load().oracle_mlp_adam_step(
+        D, H, _ptr(theta, dpt), _ptr(m, dpt), _ptr(v, dpt), t, lr, beta1,
+        beta2, eps, lo, hi, X.shape[0], _ptr(X, dpt), _ptr(T, dpt))
+    return loss, theta, m, v
+
+
+def sur_generation(pop, fit, theta, *, k, F, CR, lo, hi, seed, gen, use_model,
+                   H, O, R, bias, sigma, run0: int = 0, nthreads: int = 1):
+    """One surrogate-assisted generation; theta [runs, P] (one model per
+    run).  Returns pop_next, fit_next, cand, pred, choice, ftrial, accept."""
+    pop, fit = _f64(pop), _f64(fit)
+    runs, NP, D = pop.shape
+    theta = _f64(theta).reshape(runs, -1)
+    O, R, bias = _f64(O), _f64(R), _f64(bias)
+    out = dict(pop_next=np.empty_like(pop), fit_next=np.empty_like(fit),
+               cand=np.empty((runs, NP, k, D)), pred=np.empty((runs, NP, k)),
+               choice=np.empty((runs, NP), dtype=np.int32),
+               ftrial=np.empty_like(fit),
+               accept=np.empty((runs, NP), dtype=np.int32))
+    dpt = ctypes.c_double
+    _load().oracle_sur_generation(
+        runs, run0, NP, D, k, F, CR, lo, hi, seed, gen, int(use_model), H,
+        _ptr(theta, dpt), O.shape[0], _ptr(O, dpt), _ptr(R, dpt),
+        _ptr(bias, dpt), float(sigma), _ptr(pop, dpt), _ptr(fit, dpt),
+        _ptr(out["pop_next"], dpt), _ptr(out["fit_next"], dpt),
+        _ptr(out["cand"], dpt), _ptr(out["pred"], dpt),
+        _ptr(out["choice"], ctypes.c_int32), _ptr(out["ftrial"], dpt),
+        _ptr(out["accept"], ctypes.c_int32), nthreads)
+    return out

@@ -392,6 +392,265 @@ int oracle_run(int runs, int NP, int D, double F, double CR, double lo,
   return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Composition objective (Section 7.3.1, composition functions):
+ *     f(x) = sum_k omega_k (g_k(x) + bias_k),  omega_k = w_k / sum_j w_j,
+ * g_k the rotated oscillating function with shift O[k] and rotation R[k]
+ * (D x D row-major, k-th block of R).  Weights, as in the surrogate
+ * benchmark configuration: w_k = exp(-d_k / (2 sigma^2)) with
+ * d_k = ||x - O[k]||^2 (the paper's 1/sqrt(d_k) factor and the D in the
+ * exponent are dropped: the former is singular at x = O[k]).  Every exponent
+ * is shifted by min_k d_k, which cancels in the normalisation and keeps the
+ * largest weight at 1 (no underflow of all weights far from every O[k]).   */
+double oracle_composition(int D, int n, const double* x, const double* O,
+                          const double* R, const double* bias, double sigma) {
+  double d[64], g[64];
+  double dmin = INFINITY;
+  for (int k = 0; k < n; ++k) {
+    double dk = 0.0;
+    for (int j = 0; j < D; ++j) {
+      double y = x[j] - O[(size_t)k * D + j];
+      dk += y * y;
+    }
+    d[k] = dk;
+    if (dk < dmin) dmin = dk;
+    g[k] = oracle_objective(OR_OBJ_ROT_OSC, D, x, O + (size_t)k * D,
+                            R + (size_t)k * D * D);
+  }
+  double wsum = 0.0, f = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double w = exp(-(d[k] - dmin) / (2.0 * sigma * sigma));
+    wsum += w;
+    f += w * (g[k] + bias[k]);
+  }
+  return f / wsum;
+}
+
+void oracle_composition_batch(int D, int n, int64_t rows, const double* X,
+                              const double* O, const double* R,
+                              const double* bias, double sigma, double* f,
+                              int nthreads) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int64_t t = 0; t < rows; ++t)
+    f[t] = oracle_composition(D, n, X + t * D, O, R, bias, sigma);
+  (void)nthreads;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Surrogate MLP D -> H -> H -> 1 with ReLU (the online-trained fitness
+ * model of the surrogate-assisted variant).  Parameters packed as
+ *     theta = [W1 (H x D) | b1 (H) | W2 (H x H) | b2 (H) | w3 (H) | b3],
+ * W row-major (a = W h).  Input scaled to [-1, 1]:
+ * xs_j = (2 x_j - (lo + hi)) / (hi - lo).                                  */
+static int64_t or_mlp_size(int D, int H) {
+  return (int64_t)H * D + H + (int64_t)H * H + H + H + 1;
+}
+
+int64_t oracle_mlp_size(int D, int H) { return or_mlp_size(D, H); }
+
+/* One row: fills h1, h2 (after ReLU) and a1, a2 (before) when non-NULL. */
+static double or_mlp_row(int D, int H, const double* th, double lo, double hi,
+                         const double* x, double* xs, double* a1, double* h1,
+                         double* a2, double* h2) {
+  const double* W1 = th;
+  const double* b1 = W1 + (size_t)H * D;
+  const double* W2 = b1 + H;
+  const double* b2 = W2 + (size_t)H * H;
+  const double* w3 = b2 + H;
+  const double b3 = w3[H];
+  for (int j = 0; j < D; ++j) xs[j] = (2.0 * x[j] - (lo + hi)) / (hi - lo);
+  for (int i = 0; i < H; ++i) {
+    double a = b1[i];
+    for (int j = 0; j < D; ++j) a += W1[(size_t)i * D + j] * xs[j];
+    a1[i] = a;
+    h1[i] = a > 0.0 ? a : 0.0;
+  }
+  for (int i = 0; i < H; ++i) {
+    double a = b2[i];
+    for (int j = 0; j < H; ++j) a += W2[(size_t)i * H + j] * h1[j];
+    a2[i] = a;
+    h2[i] = a > 0.0 ? a : 0.0;
+  }
+  double y = b3;
+  for (int i = 0; i < H; ++i) y += w3[i] * h2[i];
+  return y;
+}
+
+void oracle_mlp_forward(int D, int H, const double* theta, double lo,
+                        double hi, int64_t rows, const double* X, double* y) {
+  double* buf = (double*)malloc(sizeof(double) * (size_t)(D + 4 * H));
+  for (int64_t t = 0; t < rows; ++t)
+    y[t] = or_mlp_row(D, H, theta, lo, hi, X + t * D, buf, buf + D,
+                      buf + D + H, buf + D + 2 * H, buf + D + 3 * H);
+  free(buf);
+}
+
+/* Gradient of the mean squared error L = (1/B) sum_b (y_b - t_b)^2 with
+ * respect to theta (same packing), by backpropagation; returns L.         */
+double oracle_mlp_grad(int D, int H, const double* theta, double lo,
+                       double hi, int B, const double* X, const double* T,
+                       double* grad) {
+  const int64_t P = or_mlp_size(D, H);
+  memset(grad, 0, sizeof(double) * (size_t)P);
+  const double* W2 = theta + (size_t)H * D + H;
+  const double* w3 = W2 + (size_t)H * H + H;
+  double* gW1 = grad;
+  double* gb1 = gW1 + (size_t)H * D;
+  double* gW2 = gb1 + H;
+  double* gb2 = gW2 + (size_t)H * H;
+  double* gw3 = gb2 + H;
+  double* gb3 = gw3 + H;
+  double* buf = (double*)malloc(sizeof(double) * (size_t)(D + 6 * H));
+  double* xs = buf;
+  double* a1 = xs + D;
+  double* h1 = a1 + H;
+  double* a2 = h1 + H;
+  double* h2 = a2 + H;
+  double* d2 = h2 + H;
+  double* d1 = d2 + H;
+  double loss = 0.0;
+  for (int b = 0; b < B; ++b) {
+    double y = or_mlp_row(D, H, theta, lo, hi, X + (size_t)b * D, xs, a1, h1,
+                          a2, h2);
+    double r = y - T[b];
+    loss += r * r;
+    double e = 2.0 * r / B;
+    *gb3 += e;
+    for (int i = 0; i < H; ++i) {
+      gw3[i] += e * h2[i];
+      d2[i] = a2[i] > 0.0 ? e * w3[i] : 0.0;
+      gb2[i] += d2[i];
+      for (int j = 0; j < H; ++j) gW2[(size_t)i * H + j] += d2[i] * h1[j];
+    }
+    for (int j = 0; j < H; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < H; ++i) s += W2[(size_t)i * H + j] * d2[i];
+      d1[j] = a1[j] > 0.0 ? s : 0.0;
+      gb1[j] += d1[j];
+      for (int k = 0; k < D; ++k) gW1[(size_t)j * D + k] += d1[j] * xs[k];
+    }
+  }
+  free(buf);
+  return loss / B;
+}
+
+/* One Adam step (Kingma & Ba, 2015) on the minibatch (X, T): step counter
+ * t >= 1, moments m, v updated in place, bias-corrected update
+ * theta -= lr * mhat / (sqrt(vhat) + eps).  Returns the loss before it.   */
+double oracle_mlp_adam_step(int D, int H, double* theta, double* m,
+                            double* v, int64_t t, double lr, double beta1,
+                            double beta2, double eps, double lo, double hi,
+                            int B, const double* X, const double* T) {
+  const int64_t P = or_mlp_size(D, H);
+  double* g = (double*)malloc(sizeof(double) * (size_t)P);
+  double loss = oracle_mlp_grad(D, H, theta, lo, hi, B, X, T, g);
+  const double c1 = 1.0 - pow(beta1, (double)t);
+  const double c2 = 1.0 - pow(beta2, (double)t);
+  for (int64_t p = 0; p < P; ++p) {
+    m[p] = beta1 * m[p] + (1.0 - beta1) * g[p];
+    v[p] = beta2 * v[p] + (1.0 - beta2) * g[p] * g[p];
+    theta[p] -= lr * (m[p] / c1) / (sqrt(v[p] / c2) + eps);
+  }
+  free(g);
+  return loss;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Surrogate-assisted generation: every target i builds k DE/rand/1/bin
+ * trials (candidate c draws with individual field i | c << 24 of the
+ * counter, so candidate 0 is the plain trial), the surrogate (theta of the
+ * run) predicts each candidate's scaled fitness, the candidate with the
+ * lowest prediction (lowest c on ties; c = 0 when use_model is 0) is the
+ * only one evaluated on the composition objective, and selection is the
+ * usual strict comparison.  Outputs as oracle_generation, plus (nullable)
+ * cand [runs][NP][k][D], pred [runs][NP][k] and choice [runs][NP].        */
+static void or_draw_indices_ctr(uint64_t seed, uint32_t run, int64_t gen,
+                                uint32_t ctr_i, int i, int NP, int D,
+                                int32_t out[4]) {
+  uint32_t w[4];
+  or_draw(seed, OR_TAG_IDX, run, (uint32_t)gen, ctr_i, 0u, w);
+  int a = (int)oracle_uniform_index(w[0], (uint32_t)(NP - 1));
+  int b = (int)oracle_uniform_index(w[1], (uint32_t)(NP - 2));
+  int c = (int)oracle_uniform_index(w[2], (uint32_t)(NP - 3));
+  oracle_skip_triple(i, a, b, c, out);
+  out[3] = (int32_t)oracle_uniform_index(w[3], (uint32_t)D);
+}
+
+static int or_take_ctr(uint64_t seed, uint32_t run, int64_t gen,
+                       uint32_t ctr_i, int j, int jrand, double CR) {
+  if (j == jrand) return 1;
+  uint32_t w[4];
+  or_draw(seed, OR_TAG_XOVER, run, (uint32_t)gen, ctr_i, (uint32_t)(j >> 2),
+          w);
+  return (w[j & 3] >> 8) <= or_cr_threshold(CR);
+}
+
+void oracle_sur_generation(int runs, int run0, int NP, int D, int k, double F,
+                           double CR, double lo, double hi, uint64_t seed,
+                           int64_t gen, int use_model, int H,
+                           const double* theta, int n, const double* O,
+                           const double* R, const double* bias, double sigma,
+                           const double* pop, const double* fit,
+                           double* pop_next, double* fit_next, double* cand,
+                           double* pred, int32_t* choice, double* ftrial,
+                           int32_t* accept, int nthreads) {
+  const int64_t P = or_mlp_size(D, H);
+  int64_t total = (int64_t)runs * NP;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int64_t t = 0; t < total; ++t) {
+    int r = (int)(t / NP), i = (int)(t % NP);
+    const double* Pp = pop + (size_t)r * NP * D;
+    const double* x = Pp + (size_t)i * D;
+    double* u = (double*)malloc(sizeof(double) * (size_t)k * D);
+    double* buf = (double*)malloc(sizeof(double) * (size_t)(D + 4 * H));
+    int best_c = 0;
+    double best_p = INFINITY;
+    for (int c = 0; c < k; ++c) {
+      const uint32_t ci = (uint32_t)i | ((uint32_t)c << 24);
+      int32_t d[4];
+      or_draw_indices_ctr(seed, (uint32_t)(run0 + r), gen, ci, i, NP, D, d);
+      double* uc = u + (size_t)c * D;
+      for (int j = 0; j < D; ++j) {
+        if (or_take_ctr(seed, (uint32_t)(run0 + r), gen, ci, j, d[3], CR)) {
+          double v = Pp[(size_t)d[0] * D + j] +
+                     F * (Pp[(size_t)d[1] * D + j] - Pp[(size_t)d[2] * D + j]);
+          if (v < lo) v = lo;
+          if (v > hi) v = hi;
+          uc[j] = v;
+        } else {
+          uc[j] = x[j];
+        }
+      }
+      double p = 0.0;
+      if (use_model)
+        p = or_mlp_row(D, H, theta + (size_t)r * P, lo, hi, uc, buf, buf + D,
+                       buf + D + H, buf + D + 2 * H, buf + D + 3 * H);
+      if (pred) pred[t * k + c] = p;
+      if (cand) memcpy(cand + ((size_t)t * k + c) * D, uc, sizeof(double) * D);
+      if (use_model && p < best_p) {
+        best_p = p;
+        best_c = c;
+      }
+    }
+    const double* uc = u + (size_t)best_c * D;
+    double fu = oracle_composition(D, n, uc, O, R, bias, sigma);
+    double fx = fit[t];
+    int acc = fu < fx;
+    memcpy(pop_next + (size_t)t * D, acc ? uc : x, sizeof(double) * D);
+    fit_next[t] = acc ? fu : fx;
+    if (choice) choice[t] = best_c;
+    if (ftrial) ftrial[t] = fu;
+    if (accept) accept[t] = acc;
+    free(u);
+    free(buf);
+  }
+  (void)nthreads;
+}
+
 /* Threads the OpenMP runtime would give a parallel region (1 without it). */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

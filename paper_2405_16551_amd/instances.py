@@ -73,3 +73,24 @@ def make_mixed_instances(specs, obj_seed: int = 1):
     """One rotated-objective instance (o, R) per distinct D of `specs`."""
     return {D: make_instance("rot_osc", D, obj_seed)
             for D in sorted({s[1] for s in specs})}
+
+
+COMPOSITION_SIGMA = 50.0
+
+
+def make_composition(D: int, n: int = 8, obj_seed: int = 1):
+    """Composition of n rotated oscillating components (Section 7.3.1
+    composition functions): shifts O [n, D] ~ U[-80, 80], Haar rotations
+    R [n, D, D] (float32), biases 100 k (the component with the smallest
+    bias holds the global optimum, as in the paper's definition), weight
+    width sigma = 50.  Returns (O, R, bias, sigma)."""
+    O = np.stack([_rng(obj_seed, D, 2 + 2 * k).uniform(
+        SHIFT_LO, SHIFT_HI, size=D) for k in range(n)]).astype(np.float32)
+    R = []
+    for k in range(n):
+        g = _rng(obj_seed, D, 3 + 2 * k).standard_normal((D, D))
+        q, r = np.linalg.qr(g)
+        R.append(q * np.sign(np.diag(r))[None, :])
+    R = np.ascontiguousarray(np.stack(R).astype(np.float32))
+    bias = (100.0 * np.arange(n)).astype(np.float32)
+    return O, R, bias, COMPOSITION_SIGMA

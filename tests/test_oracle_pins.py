@@ -538,3 +538,164 @@ def test_jde_trial_uses_the_rows_own_parameters():
             for j in range(6):
                 take = oracle.take_mutant(9, r, 4, i, j, jr, CRi)
                 assert out["trial"][r, i, j] == (m[j] if take else pop[r, i, j])
+
+
+# --------------------------------------------------------------------------
+# Surrogate-assisted variant: composition objective (Section 7.3.1
+# composition functions), the MLP surrogate and the pre-screened generation.
+
+def _comp(D=6, n=3, seed=2):
+    rng = np.random.default_rng(seed)
+    O = rng.uniform(-80, 80, (n, D))
+    R = np.stack([instances.make_rotation(D, 10 + k).astype(np.float64)
+                  for k in range(n)])
+    bias = 100.0 * np.arange(n)
+    return O, R, bias
+
+
+def test_composition_of_one_component_is_that_component():
+    O, R, bias = _comp(n=1)
+    X = np.random.default_rng(0).uniform(LO, HI, (20, 6))
+    f = oracle.composition_batch(X, O, R, bias + 7.0, 50.0)
+    g = oracle.objective_batch(1, X, O[0], R[0])
+    np.testing.assert_allclose(f, g + 7.0, rtol=1e-14)
+
+
+def test_composition_of_identical_components_averages_the_biases():
+    O, R, bias = _comp(n=4)
+    O[:] = O[0]
+    R[:] = R[0]
+    X = np.random.default_rng(1).uniform(LO, HI, (20, 6))
+    f = oracle.composition_batch(X, O, R, bias, 50.0)
+    g = oracle.objective_batch(1, X, O[0], R[0])
+    np.testing.assert_allclose(f, g + bias.mean(), rtol=1e-13)
+
+
+def test_composition_weights_closed_form_and_optimum():
+    O, R, bias = _comp(n=3)
+    X = np.random.default_rng(2).uniform(LO, HI, (10, 6))
+    f = oracle.composition_batch(X, O, R, bias, 30.0)
+    for x, fx in zip(X, f):
+        d = ((x - O) ** 2).sum(axis=1)
+        w = np.exp(-d / (2 * 30.0 ** 2))
+        g = np.array([oracle.objective(1, x, O[k], R[k]) for k in range(3)])
+        assert fx == pytest.approx((w * (g + bias)).sum() / w.sum(),
+                                   rel=1e-12)
+    # far from the others, component 0's shift is its optimum, f ~ bias_0 = 0
+    Oc, Rc, bc, sc = instances.make_composition(100, 8, 1)
+    f0 = oracle.composition_batch(Oc[0:1].astype(np.float64), Oc, Rc, bc, sc)
+    assert 0.0 <= f0[0] < 1e-20
+    # and it is invariant to the order of the components
+    p = [2, 0, 1]
+    np.testing.assert_allclose(oracle.composition_batch(X, O[p], R[p],
+                                                        bias[p], 30.0), f,
+                               rtol=1e-13)
+
+
+def _mlp(D=5, H=7, seed=3):
+    rng = np.random.default_rng(seed)
+    P = oracle.mlp_size(D, H)
+    assert P == H * D + H + H * H + H + H + 1
+    return rng.normal(0, 0.5, P)
+
+
+def test_mlp_forward_equals_matrix_products():
+    D, H, lo, hi = 5, 7, -100.0, 100.0
+    th = _mlp(D, H)
+    X = np.random.default_rng(4).uniform(lo, hi, (9, D))
+    W1 = th[:H * D].reshape(H, D)
+    b1 = th[H * D:H * D + H]
+    o = H * D + H
+    W2 = th[o:o + H * H].reshape(H, H)
+    b2 = th[o + H * H:o + H * H + H]
+    w3 = th[o + H * H + H:o + H * H + 2 * H]
+    b3 = th[-1]
+    xs = (2 * X - (lo + hi)) / (hi - lo)
+    h1 = np.maximum(xs @ W1.T + b1, 0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0)
+    np.testing.assert_allclose(oracle.mlp_forward(th, X, D=D, H=H, lo=lo,
+                                                  hi=hi), h2 @ w3 + b3,
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_mlp_gradient_matches_finite_differences():
+    D, H = 5, 7
+    th = _mlp(D, H, seed=5)
+    rng = np.random.default_rng(6)
+    X = rng.uniform(LO, HI, (4, D))
+    T = rng.normal(0, 1, 4)
+    loss, g = oracle.mlp_grad(th, X, T, D=D, H=H, lo=LO, hi=HI)
+    h = 1e-6
+    for p in range(th.size):
+        e = np.zeros_like(th)
+        e[p] = h
+        lp, _ = oracle.mlp_grad(th + e, X, T, D=D, H=H, lo=LO, hi=HI)
+        lm, _ = oracle.mlp_grad(th - e, X, T, D=D, H=H, lo=LO, hi=HI)
+        assert g[p] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-7)
+    y = oracle.mlp_forward(th, X, D=D, H=H, lo=LO, hi=HI)
+    assert loss == pytest.approx(np.mean((y - T) ** 2), rel=1e-12)
+
+
+def test_adam_first_step_closed_form():
+    D, H = 5, 7
+    th = _mlp(D, H, seed=7)
+    rng = np.random.default_rng(8)
+    X, T = rng.uniform(LO, HI, (6, D)), rng.normal(0, 1, 6)
+    _, g = oracle.mlp_grad(th, X, T, D=D, H=H, lo=LO, hi=HI)
+    z = np.zeros_like(th)
+    _, th1, m, v = oracle.mlp_adam_step(th, z, z, 1, X, T, D=D, H=H, lo=LO,
+                                        hi=HI, lr=1e-3, beta1=0.9,
+                                        beta2=0.999, eps=1e-8)
+    # bias-corrected first moments are g and g^2
+    np.testing.assert_allclose(th1, th - 1e-3 * g / (np.abs(g) + 1e-8),
+                               rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-12)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_surrogate_generation_structure():
+    D, H, NP, k, seed, gen = 6, 7, 9, 4, 3, 2
+    O, R, bias = _comp(D=D)
+    pop = oracle.init_population(2, NP, D, LO, HI, seed)
+    fit = oracle.composition_batch(pop.reshape(-1, D), O, R, bias,
+                                   50.0).reshape(2, NP)
+    th = np.stack([_mlp(D, H, 11), _mlp(D, H, 12)])
+    out = oracle.sur_generation(pop, fit, th, k=k, F=0.6, CR=0.7, lo=LO,
+                                hi=HI, seed=seed, gen=gen, use_model=True,
+                                H=H, O=O, R=R, bias=bias, sigma=50.0, run0=5)
+    # candidate 0 is the plain DE trial of the same generation
+    plain = oracle.generation(pop, fit, F=0.6, CR=0.7, lo=LO, hi=HI,
+                              seed=seed, gen=gen, kind=1, o=O[0], R=R[0],
+                              run0=5)
+    np.testing.assert_array_equal(out["cand"][:, :, 0], plain["trial"])
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint32)
+    for r in range(2):
+        for i in range(NP):
+            for c in range(k):
+                # candidate c: draws of counter individual field i | c << 24
+                w = oracle.philox([0, i | (c << 24), gen, (2 << 24) | (5 + r)],
+                                  key)[0]
+                a, b, cc = (oracle.uniform_index(int(w[0]), NP - 1),
+                            oracle.uniform_index(int(w[1]), NP - 2),
+                            oracle.uniform_index(int(w[2]), NP - 3))
+                r1, r2, r3 = oracle.skip_triple(i, a, b, cc)
+                jr = oracle.uniform_index(int(w[3]), D)
+                m = np.clip(pop[r, r1] + 0.6 * (pop[r, r2] - pop[r, r3]), LO, HI)
+                u = out["cand"][r, i, c]
+                assert u[jr] == m[jr]
+                assert all(u[j] in (m[j], pop[r, i, j]) for j in range(D))
+            pred = oracle.mlp_forward(th[r], out["cand"][r, i], D=D, H=H,
+                                      lo=LO, hi=HI)
+            np.testing.assert_allclose(out["pred"][r, i], pred, rtol=1e-14)
+            ch = out["choice"][r, i]
+            assert ch == int(np.argmin(pred))
+            fu = oracle.composition_batch(out["cand"][r, i, ch][None], O, R,
+                                          bias, 50.0)[0]
+            assert out["ftrial"][r, i] == fu
+            assert out["accept"][r, i] == (fu < fit[r, i])
+    # without the model the plain trial is the one evaluated
+    out0 = oracle.sur_generation(pop, fit, th, k=k, F=0.6, CR=0.7, lo=LO,
+                                 hi=HI, seed=seed, gen=gen, use_model=False,
+                                 H=H, O=O, R=R, bias=bias, sigma=50.0, run0=5)
+    assert (out0["choice"] == 0).all()
+    np.testing.assert_array_equal(out0["cand"][:, :, 0], plain["trial"])
