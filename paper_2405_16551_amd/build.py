@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libde.so")
-SOURCES = ["de_kernels.hip", "de_api.hip", "de_batch.hip"]
+SOURCES = ["de_kernels.hip", "de_api.hip", "de_batch.hip", "de_surrogate.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -15,7 +15,14 @@
 
 namespace de {
 
-enum : uint32_t { kTagInit = 1u, kTagIdx = 2u, kTagXover = 3u, kTagJde = 4u };
+enum : uint32_t {
+  kTagInit = 1u,
+  kTagIdx = 2u,
+  kTagXover = 3u,
+  kTagJde = 4u,
+  kTagTrain = 5u,   // surrogate: minibatch rows
+  kTagModel = 6u    // surrogate: initial weights
+};
 
 // Philox4x32-10 multipliers and Weyl key increments (Salmon et al., Sec. 4).
 constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
@@ -79,12 +86,12 @@ struct Donors {
   int r1, r2, r3, jrand;
 };
 
-__host__ __device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t gen,
-                                              int i, int NP, int D,
-                                              uint32_t key_lo,
-                                              uint32_t key_hi) {
-  const Words4 w = draw_block(kTagIdx, run, gen, (uint32_t)i, 0u, key_lo,
-                              key_hi);
+// ctr_i is the counter's individual field (i itself, or i | c << 24 for
+// candidate c of the surrogate-assisted step); i is the target to avoid.
+__host__ __device__ __forceinline__ Donors pick_donors_ctr(
+    uint32_t run, uint32_t gen, uint32_t ctr_i, int i, int NP, int D,
+    uint32_t key_lo, uint32_t key_hi) {
+  const Words4 w = draw_block(kTagIdx, run, gen, ctr_i, 0u, key_lo, key_hi);
   Donors d;
   const int a = uniform_below(w.w[0], (uint32_t)(NP - 1));
   d.r1 = a + (a >= i ? 1 : 0);
@@ -104,6 +111,13 @@ __host__ __device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t ge
   d.r3 = c;
   d.jrand = uniform_below(w.w[3], (uint32_t)D);
   return d;
+}
+
+__host__ __device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t gen,
+                                              int i, int NP, int D,
+                                              uint32_t key_lo,
+                                              uint32_t key_hi) {
+  return pick_donors_ctr(run, gen, (uint32_t)i, i, NP, D, key_lo, key_hi);
 }
 
 // Crossover test of eq. 3 for coordinate j = 4q + b: rand_j = (w >> 8) 2^-24

@@ -1,0 +1,1290 @@
+// de_surrogate.hip -- surrogate-assisted DE/rand/1/bin on a composition
+// objective (the C ABI of include/de_surrogate.h).
+//
+// One generation of every run:
+//   k_sur_cand     k DE/rand/1/bin candidates per target (Section 2, eqs. 2
+//                  and 3; candidate c draws with individual field i | c<<24)
+//   k_mlp_infer    the run's MLP D -> H -> H -> 1 on every candidate, BF16
+//                  32x32x16 MFMA with FP32 accumulation, bias and ReLU
+//                  fused; one workgroup per 32 candidates
+//   k_sur_select   per target the lowest prediction is evaluated on the
+//                  composition objective (Section 7.3.1 composition
+//                  functions; the expensive step), strict selection, next
+//                  generation, statistics, archive insert
+// then `steps` Adam steps of every run's model (FP32):
+//   k_train_fwd    minibatch rows drawn from the archive, forward pass,
+//                  output error and both hidden-layer deltas (16 rows per
+//                  workgroup, one thread per hidden unit)
+//   k_train_adam   one thread per parameter: its gradient summed over the
+//                  minibatch in row order, then the Adam update
+//   k_model_prep   BF16 fragment copies for inference and FP32 transposed
+//                  copies for the next forward pass
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "de.h"
+#include "de_device.hpp"
+#include "de_internal.h"
+#include "de_surrogate.h"
+#include "de_tile.hpp"
+
+namespace de {
+
+struct SurArgs {
+  // population (generation g -> g+1)
+  const float* pop_cur;
+  float* pop_next;
+  const float* fit_cur;
+  float* fit_next;
+  int runs, NP, D, ldx, k, H, Dp, pstride;
+  float F, lo, hi, xs_mul, xs_add;  // xs = x * xs_mul + xs_add
+  uint32_t cr_threshold, gen, key_lo, key_hi;
+  // composition
+  const float* O;    // [n][D]
+  const float* Rt;   // [n][D][D], Rt[c][j][i] = R[c][i][j]
+  const float* bias; // [n]
+  int n;
+  float inv2s2;      // 1 / (2 sigma^2)
+  // candidates and predictions
+  float* cand;       // [runs][NP*k][ldx]
+  float* pred;       // [runs][NP*k]
+  int* choice;       // [runs][NP]
+  int use_model;
+  // model (per run, stride pstride floats)
+  float* theta;
+  float* m;
+  float* v;
+  __bf16* w1f;       // [runs][H/32][Dp/16][64][8]
+  __bf16* w2f;       // [runs][H/32][H/16][64][8]
+  float* w1t;        // [runs][D][H]
+  float* w2t;        // [runs][H][H]
+  // archive
+  float* ax;         // [runs][cap][ldx]
+  float* at;         // [runs][cap]
+  int cap, round, filled;
+  // training
+  int B;
+  uint32_t step, mkey_lo, mkey_hi;
+  float lr, beta1, beta2, eps, c1, c2;
+  float* xsb;        // [runs][B][Dp]
+  float* h1b;        // [runs][B][H]
+  float* h2b;
+  float* d1b;
+  float* d2b;
+  float* eb;         // [runs][B]
+  // statistics
+  unsigned long long* best_key;
+  unsigned long long* accepted;
+};
+
+constexpr int kEvalRows = 8;
+constexpr int kEvalThreads = 128;
+constexpr int kMaxComp = 64;
+
+// ---------------------------------------------------------------------------
+// Composition objective of up to kEvalRows rows (pointers in rowp), one
+// workgroup of kEvalThreads threads.  Per component: y = x - O[c] into LDS
+// with ||y||^2, z = R[c] y with one thread per output coordinate reading
+// the transposed rotation (coalesced), g = sum z^2 + sin^2(3z); partial
+// sums reduced in a fixed order.  Then the normalised weights.
+__device__ void comp_eval_rows(const SurArgs& a, const float* const* rowp,
+                               int nv, float* sm, float* fout) {
+  const int tid = (int)threadIdx.x, lane = tid % 64, wave = tid / 64;
+  constexpr int kWaves = kEvalThreads / 64;
+  const int D = a.D;
+  float* xs = sm;                          // [rows][D]
+  float* ys = xs + kEvalRows * D;          // [rows][D]
+  float* dk = ys + kEvalRows * D;          // [n][rows]
+  float* gk = dk + kMaxComp * kEvalRows;   // [n][rows]
+  float* red = gk + kMaxComp * kEvalRows;  // [2][rows][waves]
+  for (int t = tid; t < kEvalRows * D; t += kEvalThreads) {
+    const int r = t / D, j = t - r * D;
+    xs[t] = r < nv ? rowp[r][j] : 0.f;
+  }
+  __syncthreads();
+  for (int c = 0; c < a.n; ++c) {
+    const float* o = a.O + (size_t)c * D;
+    const float* rt = a.Rt + (size_t)c * D * D;
+    float dpart[kEvalRows], gpart[kEvalRows];
+#pragma unroll
+    for (int r = 0; r < kEvalRows; ++r) dpart[r] = gpart[r] = 0.f;
+    for (int j = tid; j < D; j += kEvalThreads) {
+      const float oj = o[j];
+#pragma unroll
+      for (int r = 0; r < kEvalRows; ++r) {
+        const float y = xs[r * D + j] - oj;
+        ys[r * D + j] = y;
+        dpart[r] = fmaf(y, y, dpart[r]);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < D; i += kEvalThreads) {
+      float z[kEvalRows];
+#pragma unroll
+      for (int r = 0; r < kEvalRows; ++r) z[r] = 0.f;
+      for (int j = 0; j < D; ++j) {
+        const float rv = rt[(size_t)j * D + i];
+#pragma unroll
+        for (int r = 0; r < kEvalRows; ++r) z[r] = fmaf(rv, ys[r * D + j], z[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < kEvalRows; ++r)
+        gpart[r] += fmaf(z[r], z[r], sin_squared(3.0f * z[r]));
+    }
+#pragma unroll
+    for (int r = 0; r < kEvalRows; ++r) {
+      const float ds = group_sum<64>(dpart[r]);
+      const float gs = group_sum<64>(gpart[r]);
+      if (lane == 0) {
+        red[(0 * kEvalRows + r) * kWaves + wave] = ds;
+        red[(1 * kEvalRows + r) * kWaves + wave] = gs;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * kEvalRows) {
+      float s = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s += red[tid * kWaves + w];
+      const int q = tid / kEvalRows, r = tid % kEvalRows;
+      (q == 0 ? dk : gk)[c * kEvalRows + r] = s;
+    }
+    __syncthreads();
+  }
+  if (tid < kEvalRows) {
+    float dmin = INFINITY;
+    for (int c = 0; c < a.n; ++c) dmin = fminf(dmin, dk[c * kEvalRows + tid]);
+    float wsum = 0.f, f = 0.f;
+    for (int c = 0; c < a.n; ++c) {
+      const float w = expf(-(dk[c * kEvalRows + tid] - dmin) * a.inv2s2);
+      wsum += w;
+      f = fmaf(w, gk[c * kEvalRows + tid] + a.bias[c], f);
+    }
+    fout[tid] = f / wsum;
+  }
+  __syncthreads();
+}
+
+__host__ __device__ constexpr size_t comp_lds_floats(int D) {
+  return (size_t)2 * kEvalRows * D + (size_t)2 * kMaxComp * kEvalRows +
+         (size_t)2 * kEvalRows * (kEvalThreads / 64) + kEvalRows;
+}
+
+// f of rows X (row r at X + r * ldx).
+__global__ __launch_bounds__(kEvalThreads) void k_comp_eval(SurArgs a,
+                                                            const float* X,
+                                                            int n, int ldx,
+                                                            float* f) {
+  extern __shared__ __align__(16) float sm[];
+  __shared__ const float* rowp[kEvalRows];
+  const int row0 = (int)blockIdx.x * kEvalRows;
+  const int nv = min(kEvalRows, n - row0);
+  if ((int)threadIdx.x < kEvalRows)
+    rowp[threadIdx.x] = X + (size_t)(row0 + min((int)threadIdx.x, nv - 1)) * ldx;
+  __syncthreads();
+  float* fout = sm + comp_lds_floats(a.D) - kEvalRows;
+  comp_eval_rows(a, rowp, nv, sm, fout);
+  if ((int)threadIdx.x < nv) f[row0 + threadIdx.x] = fout[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Candidates: one wave per candidate row (i, c), lanes over 4-groups.
+__global__ __launch_bounds__(256) void k_sur_cand(SurArgs a) {
+  const int run = (int)blockIdx.y;
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int cr = (int)blockIdx.x * 4 + wave;
+  if (cr >= a.NP * a.k) return;  // whole waves leave together
+  const int i = cr / a.k, c = cr - i * a.k;
+  const uint32_t ctr_i = (uint32_t)i | ((uint32_t)c << 24);
+  const Donors d = pick_donors_ctr((uint32_t)run, a.gen, ctr_i, i, a.NP, a.D,
+                                   a.key_lo, a.key_hi);
+  const float* base = a.pop_cur + (size_t)run * a.NP * a.ldx;
+  const float* x = base + (size_t)i * a.ldx;
+  const float* x1 = base + (size_t)d.r1 * a.ldx;
+  const float* x2 = base + (size_t)d.r2 * a.ldx;
+  const float* x3 = base + (size_t)d.r3 * a.ldx;
+  float* out = a.cand + ((size_t)run * a.NP * a.k + cr) * a.ldx;
+  const int nq = (a.D + 3) / 4;
+  for (int q = lane; q < nq; q += 64) {
+    const int j0 = 4 * q;
+    const float4 xv = ld4(x + j0), v1 = ld4(x1 + j0), v2 = ld4(x2 + j0),
+                 v3 = ld4(x3 + j0);
+    const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen, ctr_i,
+                                (uint32_t)q, a.key_lo, a.key_hi);
+    float4 u = xv;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const bool tk = (j0 + b < a.D) &&
+                      take_mutant(w.w[b], j0 + b, d.jrand, a.cr_threshold);
+      const float mv = mutant_coord(get(v1, b), get(v2, b), get(v3, b), a.F,
+                                    a.lo, a.hi);
+      set(u, b, tk ? mv : get(xv, b));
+    }
+    st4(out + j0, u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MLP inference on MFMA: rows of X (row r at X + r * ldx) of run
+// run0 + blockIdx.y, 32 rows per workgroup of 256 threads.
+constexpr int kInferRows = 32;
+
+__host__ __device__ constexpr size_t infer_lds_bytes(int Dp, int H) {
+  return (size_t)kInferRows * (Dp + 8) * 2 + (size_t)kInferRows * (H + 8) * 2 +
+         (size_t)kInferRows * H * 4;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
+                                                   size_t x_run_stride, int n,
+                                                   int ldx, float* y,
+                                                   size_t y_run_stride,
+                                                   int run0) {
+  extern __shared__ __align__(16) char smem[];
+  const int run = run0 + (int)blockIdx.y;
+  const int tid = (int)threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int row0 = (int)blockIdx.x * kInferRows;
+  const int Dp = a.Dp, H = a.H;
+  const int sa = Dp + 8, sh = H + 8;
+  __bf16* A = reinterpret_cast<__bf16*>(smem);
+  __bf16* H1 = A + (size_t)kInferRows * sa;
+  float* H2 = reinterpret_cast<float*>(H1 + (size_t)kInferRows * sh);
+  const float* Xr = X + blockIdx.y * x_run_stride;
+  const float* th = a.theta + (size_t)run * a.pstride;
+  const float* b1 = th + (size_t)H * a.D;
+  const float* b2 = b1 + H + (size_t)H * H;
+  const float* w3 = b2 + H;
+  const float b3 = w3[H];
+  for (int t = tid; t < kInferRows * Dp; t += 256) {
+    const int r = t / Dp, dd = t - r * Dp;
+    float v = 0.f;
+    if (row0 + r < n && dd < a.D)
+      v = fmaf(Xr[(size_t)(row0 + r) * ldx + dd], a.xs_mul, a.xs_add);
+    A[r * sa + dd] = (__bf16)v;
+  }
+  __syncthreads();
+  const int nblk = H / 32;
+  // layer 1: H1 = relu(A W1^T + b1), BF16
+  {
+    const int kbn = Dp / 16;
+    const bf16x8* wf = reinterpret_cast<const bf16x8*>(a.w1f) +
+                       (size_t)run * nblk * kbn * 64;
+    const __bf16* ar = A + (size_t)(lane % 32) * sa + 8 * (lane / 32);
+    for (int nb = wave; nb < nblk; nb += 4) {
+      floatx16 c = {};
+      for (int kb = 0; kb < kbn; ++kb) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(ar + 16 * kb);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            av, wf[((size_t)nb * kbn + kb) * 64 + lane], c, 0, 0, 0);
+      }
+      const int col = nb * 32 + lane % 32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        H1[row * sh + col] = (__bf16)fmaxf(c[r] + b1[col], 0.f);
+      }
+    }
+  }
+  __syncthreads();
+  // layer 2: H2 = relu(H1 W2^T + b2), FP32
+  {
+    const int kbn = H / 16;
+    const bf16x8* wf = reinterpret_cast<const bf16x8*>(a.w2f) +
+                       (size_t)run * nblk * kbn * 64;
+    const __bf16* ar = H1 + (size_t)(lane % 32) * sh + 8 * (lane / 32);
+    for (int nb = wave; nb < nblk; nb += 4) {
+      floatx16 c = {};
+      for (int kb = 0; kb < kbn; ++kb) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(ar + 16 * kb);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            av, wf[((size_t)nb * kbn + kb) * 64 + lane], c, 0, 0, 0);
+      }
+      const int col = nb * 32 + lane % 32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        H2[row * H + col] = fmaxf(c[r] + b2[col], 0.f);
+      }
+    }
+  }
+  __syncthreads();
+  // layer 3: y = H2 w3 + b3, eight lanes per row
+  {
+    const int r = tid / 8, part = tid % 8;
+    float s = 0.f;
+    for (int i = part; i < H; i += 8) s = fmaf(w3[i], H2[r * H + i], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    if (part == 0 && row0 + r < n) y[blockIdx.y * y_run_stride + row0 + r] = s + b3;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Choice, true evaluation, selection, next generation, archive insert:
+// kEvalRows targets per workgroup.
+__global__ __launch_bounds__(kEvalThreads) void k_sur_select(SurArgs a) {
+  extern __shared__ __align__(16) float sm[];
+  __shared__ const float* rowp[kEvalRows];
+  __shared__ int acc_s[kEvalRows];
+  const int run = (int)blockIdx.y;
+  const int i0 = (int)blockIdx.x * kEvalRows;
+  const int nv = min(kEvalRows, a.NP - i0);
+  const int tid = (int)threadIdx.x;
+  if (tid < kEvalRows) {
+    const int i = i0 + min(tid, nv - 1);
+    const size_t t = (size_t)run * a.NP + i;
+    int best = 0;
+    if (a.use_model) {
+      float bp = a.pred[t * a.k];
+      for (int c = 1; c < a.k; ++c) {
+        const float p = a.pred[t * a.k + c];
+        if (p < bp) {
+          bp = p;
+          best = c;
+        }
+      }
+    }
+    rowp[tid] = a.cand + (t * a.k + best) * a.ldx;
+    if (tid < nv) a.choice[t] = best;
+  }
+  __syncthreads();
+  float* fout = sm + comp_lds_floats(a.D) - kEvalRows;
+  comp_eval_rows(a, rowp, nv, sm, fout);
+  if (tid < nv) {
+    const int i = i0 + tid;
+    const size_t t = (size_t)run * a.NP + i;
+    const float fu = fout[tid], fx = a.fit_cur[t];
+    const bool accept = fu < fx;
+    a.fit_next[t] = accept ? fu : fx;
+    acc_s[tid] = accept ? 1 : 0;
+    if (accept) {
+      atomicAdd(&a.accepted[run], 1ull);
+      atomicMin(&a.best_key[run], fit_key(fu, i));
+    }
+    const int pos = (int)(((long long)a.round * a.NP + i) % a.cap);
+    a.at[(size_t)run * a.cap + pos] = log10f(fu + 1e-8f);
+  }
+  __syncthreads();
+  const int nq = (a.D + 3) / 4;
+  for (int t2 = tid; t2 < nv * nq; t2 += kEvalThreads) {
+    const int r = t2 / nq, q = t2 - r * nq;
+    const int i = i0 + r;
+    const size_t t = (size_t)run * a.NP + i;
+    const float4 u = ld4(rowp[r] + 4 * q);
+    const float4 xv = ld4(a.pop_cur + t * a.ldx + 4 * q);
+    st4(a.pop_next + t * a.ldx + 4 * q, acc_s[r] ? u : xv);
+    const int pos = (int)(((long long)a.round * a.NP + i) % a.cap);
+    st4(a.ax + ((size_t)run * a.cap + pos) * a.ldx + 4 * q, u);
+  }
+}
+
+// Generation 0 into the archive (round 0): rows and their targets.
+__global__ __launch_bounds__(256) void k_archive_init(SurArgs a) {
+  const int nq = (a.D + 3) / 4;
+  const size_t total = (size_t)a.runs * a.NP * nq;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const size_t row = t / nq;
+    const int q = (int)(t - row * nq);
+    const int run = (int)(row / a.NP), i = (int)(row - (size_t)run * a.NP);
+    const int pos = i % a.cap;
+    st4(a.ax + ((size_t)run * a.cap + pos) * a.ldx + 4 * q,
+        ld4(a.pop_cur + row * a.ldx + 4 * q));
+    if (q == 0) a.at[(size_t)run * a.cap + pos] = log10f(a.fit_cur[row] + 1e-8f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Model: initial weights (He-uniform from Philox tag 6, biases zero), BF16
+// fragment and FP32 transposed copies, training.
+__global__ __launch_bounds__(256) void k_model_init(SurArgs a, int P) {
+  const size_t total = (size_t)a.runs * a.pstride;
+  const int H = a.H, D = a.D;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int run = (int)(t / a.pstride), p = (int)(t - (size_t)run * a.pstride);
+    float bound = 0.f;
+    if (p < H * D) bound = sqrtf(6.0f / D);
+    else if (p >= H * D + H && p < H * D + H + H * H) bound = sqrtf(6.0f / H);
+    else if (p >= H * D + H + H * H + H && p < H * D + H + H * H + 2 * H)
+      bound = sqrtf(3.0f / H);
+    float val = 0.f;
+    if (bound > 0.f && p < P) {
+      const Words4 w = draw_block(kTagModel, (uint32_t)run, 0u, 0u,
+                                  (uint32_t)(p >> 2), a.mkey_lo, a.mkey_hi);
+      const int sl = p & 3;
+      const uint32_t word = sl == 0 ? w.w[0] : sl == 1 ? w.w[1]
+                            : sl == 2 ? w.w[2] : w.w[3];
+      const float u = (float)(word >> 8) * 0x1.0p-24f;
+      val = bound * fmaf(2.0f, u, -1.0f);
+    }
+    a.theta[t] = val;
+    a.m[t] = 0.f;
+    a.v[t] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_model_prep(SurArgs a) {
+  const int H = a.H, D = a.D, Dp = a.Dp;
+  const size_t per = (size_t)H * Dp + (size_t)H * H;
+  const size_t total = (size_t)a.runs * per;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int run = (int)(t / per);
+    size_t e = t - (size_t)run * per;
+    const float* th = a.theta + (size_t)run * a.pstride;
+    int n, k, K;
+    __bf16* dst;
+    float v;
+    if (e < (size_t)H * Dp) {
+      n = (int)(e / Dp);
+      k = (int)(e - (size_t)n * Dp);
+      K = Dp;
+      v = k < D ? th[(size_t)n * D + k] : 0.f;
+      dst = a.w1f + (size_t)run * H * Dp;
+      if (k < D) a.w1t[((size_t)run * D + k) * H + n] = v;
+    } else {
+      e -= (size_t)H * Dp;
+      n = (int)(e / H);
+      k = (int)(e - (size_t)n * H);
+      K = H;
+      v = th[(size_t)H * D + H + (size_t)n * H + k];
+      dst = a.w2f + (size_t)run * H * H;
+      a.w2t[((size_t)run * H + k) * H + n] = v;
+    }
+    // element (n, k) of W -> block n/32, K-step k/16, lane, slot
+    const size_t nb = n / 32, kb = k / 16;
+    const int ln = (n % 32) + 32 * ((k % 16) / 8);
+    dst[((nb * (K / 16) + kb) * 64 + ln) * 8 + (k % 8)] = (__bf16)v;
+  }
+}
+
+constexpr int kTrainRows = 16;
+
+__host__ __device__ constexpr size_t train_lds_floats(int D, int H) {
+  return (size_t)kTrainRows * D + (size_t)3 * kTrainRows * H + 2 * kTrainRows;
+}
+
+// Forward pass of 16 minibatch rows per workgroup (one thread per hidden
+// unit, H <= 256), output error e = 2 (y - t) / B and the deltas of both
+// hidden layers; everything the gradient needs goes to the scratch arrays.
+__global__ __launch_bounds__(256) void k_train_fwd(SurArgs a) {
+  extern __shared__ __align__(16) float sm[];
+  const int run = (int)blockIdx.y;
+  const int tid = (int)threadIdx.x;
+  const int H = a.H, D = a.D;
+  const int b0 = (int)blockIdx.x * kTrainRows;
+  float* xs = sm;                          // [16][D]
+  float* h1 = xs + kTrainRows * D;         // [16][H]
+  float* h2 = h1 + kTrainRows * H;
+  float* d2 = h2 + kTrainRows * H;
+  float* es = d2 + kTrainRows * H;         // [16]
+  int* src = reinterpret_cast<int*>(es + kTrainRows);  // [16]
+  const float* th = a.theta + (size_t)run * a.pstride;
+  const float* b1 = th + (size_t)H * D;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + (size_t)H * H;
+  const float* w3 = b2 + H;
+  const float b3 = w3[H];
+  const float* w1t = a.w1t + (size_t)run * D * H;
+  const float* w2t = a.w2t + (size_t)run * H * H;
+  if (tid < kTrainRows) {
+    const Words4 w = draw_block(kTagTrain, (uint32_t)run, a.step,
+                                (uint32_t)(b0 + tid), 0u, a.mkey_lo,
+                                a.mkey_hi);
+    src[tid] = uniform_below(w.w[0], (uint32_t)a.filled);
+  }
+  __syncthreads();
+  for (int t = tid; t < kTrainRows * D; t += 256) {
+    const int r = t / D, dd = t - r * D;
+    const float v = fmaf(a.ax[((size_t)run * a.cap + src[r]) * a.ldx + dd],
+                         a.xs_mul, a.xs_add);
+    xs[t] = v;
+    a.xsb[((size_t)run * a.B + b0 + r) * a.Dp + dd] = v;
+  }
+  __syncthreads();
+  const bool unit = tid < H;
+  float acc[kTrainRows];
+  if (unit) {
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r) acc[r] = b1[tid];
+    for (int dd = 0; dd < D; ++dd) {
+      const float wv = w1t[(size_t)dd * H + tid];
+#pragma unroll
+      for (int r = 0; r < kTrainRows; ++r) acc[r] = fmaf(wv, xs[r * D + dd], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r) {
+      const float hv = fmaxf(acc[r], 0.f);
+      h1[r * H + tid] = hv;
+      a.h1b[((size_t)run * a.B + b0 + r) * H + tid] = hv;
+    }
+  }
+  __syncthreads();
+  if (unit) {
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r) acc[r] = b2[tid];
+    for (int j = 0; j < H; ++j) {
+      const float wv = w2t[(size_t)j * H + tid];
+#pragma unroll
+      for (int r = 0; r < kTrainRows; ++r) acc[r] = fmaf(wv, h1[r * H + j], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r) {
+      const float hv = fmaxf(acc[r], 0.f);
+      h2[r * H + tid] = hv;
+      a.h2b[((size_t)run * a.B + b0 + r) * H + tid] = hv;
+    }
+  }
+  __syncthreads();
+  {
+    // 16 lanes per row
+    const int r = tid / 16, part = tid % 16;
+    float s = 0.f;
+    for (int i = part; i < H; i += 16) s = fmaf(w3[i], h2[r * H + i], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    s += __shfl_xor(s, 8, 64);
+    if (part == 0) {
+      const float tgt = a.at[(size_t)run * a.cap + src[r]];
+      const float e = 2.0f * (s + b3 - tgt) / (float)a.B;
+      es[r] = e;
+      a.eb[(size_t)run * a.B + b0 + r] = e;
+    }
+  }
+  __syncthreads();
+  if (unit) {
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r) {
+      const float dv = h2[r * H + tid] > 0.f ? es[r] * w3[tid] : 0.f;
+      d2[r * H + tid] = dv;
+      a.d2b[((size_t)run * a.B + b0 + r) * H + tid] = dv;
+    }
+  }
+  __syncthreads();
+  if (unit) {
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r) acc[r] = 0.f;
+    for (int i = 0; i < H; ++i) {
+      const float wv = W2[(size_t)i * H + tid];
+#pragma unroll
+      for (int r = 0; r < kTrainRows; ++r) acc[r] = fmaf(wv, d2[r * H + i], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kTrainRows; ++r)
+      a.d1b[((size_t)run * a.B + b0 + r) * H + tid] =
+          h1[r * H + tid] > 0.f ? acc[r] : 0.f;
+  }
+}
+
+// One thread per parameter: gradient summed over the minibatch rows in
+// order, then the Adam update with bias corrections c1, c2.
+__global__ __launch_bounds__(256) void k_train_adam(SurArgs a, int P) {
+  const int H = a.H, D = a.D, B = a.B;
+  const size_t total = (size_t)a.runs * P;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int run = (int)(t / P), p = (int)(t - (size_t)run * P);
+    const float* xs = a.xsb + (size_t)run * B * a.Dp;
+    const float* h1 = a.h1b + (size_t)run * B * H;
+    const float* h2 = a.h2b + (size_t)run * B * H;
+    const float* d1 = a.d1b + (size_t)run * B * H;
+    const float* d2 = a.d2b + (size_t)run * B * H;
+    const float* e = a.eb + (size_t)run * B;
+    float g = 0.f;
+    int q = p;
+    if (q < H * D) {
+      const int j = q / D, dd = q - j * D;
+      for (int b = 0; b < B; ++b)
+        g = fmaf(d1[(size_t)b * H + j], xs[(size_t)b * a.Dp + dd], g);
+    } else if ((q -= H * D) < H) {
+      for (int b = 0; b < B; ++b) g += d1[(size_t)b * H + q];
+    } else if ((q -= H) < H * H) {
+      const int i = q / H, j = q - i * H;
+      for (int b = 0; b < B; ++b)
+        g = fmaf(d2[(size_t)b * H + i], h1[(size_t)b * H + j], g);
+    } else if ((q -= H * H) < H) {
+      for (int b = 0; b < B; ++b) g += d2[(size_t)b * H + q];
+    } else if ((q -= H) < H) {
+      for (int b = 0; b < B; ++b) g = fmaf(e[b], h2[(size_t)b * H + q], g);
+    } else {
+      for (int b = 0; b < B; ++b) g += e[b];
+    }
+    const size_t at = (size_t)run * a.pstride + p;
+    const float mv = fmaf(a.beta1, a.m[at], (1.0f - a.beta1) * g);
+    const float vv = fmaf(a.beta2, a.v[at], (1.0f - a.beta2) * g * g);
+    a.m[at] = mv;
+    a.v[at] = vv;
+    a.theta[at] -= a.lr * (mv / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sur_reset(SurArgs a) {
+  for (int r = (int)(blockIdx.x * 256 + threadIdx.x); r < a.runs;
+       r += (int)(gridDim.x * 256)) {
+    a.best_key[r] = ~0ull;
+    a.accepted[r] = 0ull;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sur_best(SurArgs a) {
+  const int run = (int)blockIdx.x;
+  unsigned long long best = ~0ull;
+  for (int i = (int)threadIdx.x; i < a.NP; i += 256)
+    best = min(best, fit_key(a.fit_cur[(size_t)run * a.NP + i], i));
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long o =
+        ((unsigned long long)__shfl_xor((unsigned)(best >> 32), m, 64) << 32) |
+        (unsigned long long)__shfl_xor((unsigned)best, m, 64);
+    best = min(best, o);
+  }
+  if ((threadIdx.x % 64) == 0) atomicMin(&a.best_key[run], best);
+}
+
+// Transposed rotations Rt[c][j][i] = R[c][i][j] and shifts.
+__global__ __launch_bounds__(256) void k_comp_prep(const float* O,
+                                                   const float* R, int ldr,
+                                                   int n, int D, float* Op,
+                                                   float* Rt) {
+  const size_t per = (size_t)D * D;
+  const size_t total = (size_t)n * per;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * 256) {
+    const int c = (int)(t / per);
+    const size_t e = t - (size_t)c * per;
+    const int j = (int)(e / D), i = (int)(e - (size_t)j * D);
+    Rt[t] = R[((size_t)c * D + i) * ldr + j];
+    if (j == 0) Op[(size_t)c * D + i] = O[(size_t)c * D + i];
+  }
+}
+
+}  // namespace de
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+namespace {
+
+using de::SurArgs;
+
+constexpr uint64_t kSurMagic = 0x6465737572726721ull;
+
+size_t rup(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+int64_t model_size(int D, int H) {
+  return (int64_t)H * D + H + (int64_t)H * H + H + H + 1;
+}
+
+struct SLayout {
+  size_t best, acc, O, Rt, bias, cand, pred, choice, theta, m, v, w1f, w2f,
+      w1t, w2t, ax, at, xsb, h1b, h2b, d1b, d2b, eb, total;
+  int pstride, Dp;
+};
+
+de_status check(const de_params* p, const de_composition* c,
+                const de_surrogate_params* s) {
+  if (!p || !c || !s) return DE_E_INVAL;
+  if (p->runs < 1 || p->runs > 65535 || p->NP < 4 || p->D < 1)
+    return DE_E_INVAL;
+  if ((int64_t)p->runs * p->NP * 16 > std::numeric_limits<int32_t>::max())
+    return DE_E_INVAL;
+  if (!std::isfinite(p->F) || !(p->F > 0.f)) return DE_E_INVAL;
+  if (!(p->CR >= 0.f && p->CR <= 1.f)) return DE_E_INVAL;
+  if (!std::isfinite(p->lo) || !std::isfinite(p->hi) || !(p->lo < p->hi) ||
+      !std::isfinite(p->hi - p->lo))
+    return DE_E_INVAL;
+  if (c->n < 1 || c->n > de::kMaxComp || c->reserved != 0) return DE_E_INVAL;
+  if (c->ldr < p->D || !c->O || !c->R || !c->bias) return DE_E_INVAL;
+  if (!std::isfinite(c->sigma) || !(c->sigma > 0.f)) return DE_E_INVAL;
+  for (int k = 0; k < c->n; ++k)
+    if (!std::isfinite(c->bias[k])) return DE_E_INVAL;
+  if (s->k < 1 || s->k > 16) return DE_E_INVAL;
+  if (s->hidden < 32 || s->hidden > 256 || s->hidden % 32) return DE_E_INVAL;
+  if (s->batch < 16 || s->batch > 1024 || s->batch % 16) return DE_E_INVAL;
+  if (s->archive < s->batch || s->archive < p->NP) return DE_E_INVAL;
+  if ((int64_t)s->archive * p->runs > std::numeric_limits<int32_t>::max())
+    return DE_E_INVAL;
+  if (s->steps < 0 || s->warmup_gens < 0) return DE_E_INVAL;
+  if (!std::isfinite(s->lr) || !(s->lr > 0.f)) return DE_E_INVAL;
+  if (!(s->beta1 >= 0.f && s->beta1 < 1.f) || !(s->beta2 >= 0.f && s->beta2 < 1.f))
+    return DE_E_INVAL;
+  if (!std::isfinite(s->eps) || !(s->eps > 0.f)) return DE_E_INVAL;
+  // LDS: composition evaluation and model inference
+  if (de::comp_lds_floats(p->D) * 4 > (size_t)de::kMaxLdsBytes ||
+      de::infer_lds_bytes((int)rup(p->D, 32), s->hidden) >
+          (size_t)de::kMaxLdsBytes ||
+      de::train_lds_floats(p->D, s->hidden) * 4 > (size_t)de::kMaxLdsBytes)
+    return DE_E_UNSUPPORTED;
+  return DE_OK;
+}
+
+SLayout layout(const de_params& p, const de_composition& c,
+               const de_surrogate_params& s, int ldx) {
+  SLayout L{};
+  size_t off = 0;
+  auto take = [&off](size_t bytes) {
+    const size_t at = off;
+    off = rup(off + bytes, 256);
+    return at;
+  };
+  const size_t R = (size_t)p.runs, NP = (size_t)p.NP, D = (size_t)p.D;
+  const size_t H = (size_t)s.hidden, k = (size_t)s.k, B = (size_t)s.batch;
+  L.Dp = (int)rup(D, 32);
+  L.pstride = (int)rup((size_t)model_size(p.D, s.hidden), 64);
+  L.best = take(8 * R);
+  L.acc = take(8 * R);
+  L.O = take(4 * (size_t)c.n * D);
+  L.Rt = take(4 * (size_t)c.n * D * D);
+  L.bias = take(4 * (size_t)c.n);
+  L.cand = take(4 * R * NP * k * ldx);
+  L.pred = take(4 * R * NP * k);
+  L.choice = take(4 * R * NP);
+  L.theta = take(4 * R * L.pstride);
+  L.m = take(4 * R * L.pstride);
+  L.v = take(4 * R * L.pstride);
+  L.w1f = take(2 * R * H * L.Dp);
+  L.w2f = take(2 * R * H * H);
+  L.w1t = take(4 * R * D * H);
+  L.w2t = take(4 * R * H * H);
+  L.ax = take(4 * R * (size_t)s.archive * ldx);
+  L.at = take(4 * R * (size_t)s.archive);
+  L.xsb = take(4 * R * B * L.Dp);
+  L.h1b = take(4 * R * B * H);
+  L.h2b = take(4 * R * B * H);
+  L.d1b = take(4 * R * B * H);
+  L.d2b = take(4 * R * B * H);
+  L.eb = take(4 * R * B);
+  L.total = off;
+  return L;
+}
+
+de_status from_hip(hipError_t e) {
+  return e == hipSuccess ? DE_OK : DE_E_DEVICE;
+}
+
+int grid_for(size_t work, int per) {
+  size_t b = (work + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (int)b;
+}
+
+}  // namespace
+
+struct de_sur {
+  uint64_t magic = kSurMagic;
+  de_params p{};
+  de_surrogate_params sp{};
+  int n = 0, ldx = 0;
+  float sigma = 0.f;
+  float* pop[2] = {nullptr, nullptr};
+  float* fit[2] = {nullptr, nullptr};
+  char* work = nullptr;
+  SLayout L{};
+  int64_t gen = 0;
+  int64_t step = 0;  // Adam steps taken
+  int64_t rounds = 1;  // archive insert rounds done (generation 0 is one)
+  int last_use_model = 0;
+};
+
+namespace {
+
+std::mutex g_mu;
+std::set<const de_sur*>& live_set() {
+  static std::set<const de_sur*> s;
+  return s;
+}
+
+bool live(const de_sur* s) {
+  if (!s) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return live_set().count(s) != 0 && s->magic == kSurMagic;
+}
+
+SurArgs args_of(const de_sur* s) {
+  SurArgs a{};
+  char* w = s->work;
+  const SLayout& L = s->L;
+  const int b = (int)(s->gen & 1);
+  a.pop_cur = s->pop[b];
+  a.pop_next = s->pop[b ^ 1];
+  a.fit_cur = s->fit[b];
+  a.fit_next = s->fit[b ^ 1];
+  a.runs = s->p.runs;
+  a.NP = s->p.NP;
+  a.D = s->p.D;
+  a.ldx = s->ldx;
+  a.k = s->sp.k;
+  a.H = s->sp.hidden;
+  a.Dp = L.Dp;
+  a.pstride = L.pstride;
+  a.F = s->p.F;
+  a.lo = s->p.lo;
+  a.hi = s->p.hi;
+  a.xs_mul = 2.0f / (s->p.hi - s->p.lo);
+  a.xs_add = -(s->p.lo + s->p.hi) / (s->p.hi - s->p.lo);
+  a.cr_threshold = (uint32_t)std::floor((double)s->p.CR * 16777216.0);
+  a.gen = (uint32_t)s->gen;
+  a.key_lo = (uint32_t)s->p.seed;
+  a.key_hi = (uint32_t)(s->p.seed >> 32);
+  a.O = reinterpret_cast<const float*>(w + L.O);
+  a.Rt = reinterpret_cast<const float*>(w + L.Rt);
+  a.bias = reinterpret_cast<const float*>(w + L.bias);
+  a.n = s->n;
+  a.inv2s2 = (float)(1.0 / (2.0 * (double)s->sigma * s->sigma));
+  a.cand = reinterpret_cast<float*>(w + L.cand);
+  a.pred = reinterpret_cast<float*>(w + L.pred);
+  a.choice = reinterpret_cast<int*>(w + L.choice);
+  a.theta = reinterpret_cast<float*>(w + L.theta);
+  a.m = reinterpret_cast<float*>(w + L.m);
+  a.v = reinterpret_cast<float*>(w + L.v);
+  a.w1f = reinterpret_cast<__bf16*>(w + L.w1f);
+  a.w2f = reinterpret_cast<__bf16*>(w + L.w2f);
+  a.w1t = reinterpret_cast<float*>(w + L.w1t);
+  a.w2t = reinterpret_cast<float*>(w + L.w2t);
+  a.ax = reinterpret_cast<float*>(w + L.ax);
+  a.at = reinterpret_cast<float*>(w + L.at);
+  a.cap = s->sp.archive;
+  a.round = (int)s->rounds;
+  a.filled = (int)std::min<int64_t>(s->sp.archive, s->rounds * s->p.NP);
+  a.B = s->sp.batch;
+  a.step = (uint32_t)s->step;
+  a.mkey_lo = (uint32_t)s->sp.model_seed;
+  a.mkey_hi = (uint32_t)(s->sp.model_seed >> 32);
+  a.lr = s->sp.lr;
+  a.beta1 = s->sp.beta1;
+  a.beta2 = s->sp.beta2;
+  a.eps = s->sp.eps;
+  a.xsb = reinterpret_cast<float*>(w + L.xsb);
+  a.h1b = reinterpret_cast<float*>(w + L.h1b);
+  a.h2b = reinterpret_cast<float*>(w + L.h2b);
+  a.d1b = reinterpret_cast<float*>(w + L.d1b);
+  a.d2b = reinterpret_cast<float*>(w + L.d2b);
+  a.eb = reinterpret_cast<float*>(w + L.eb);
+  a.best_key = reinterpret_cast<unsigned long long*>(w + L.best);
+  a.accepted = reinterpret_cast<unsigned long long*>(w + L.acc);
+  return a;
+}
+
+de_status set_lds_attributes() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    const void* fns[] = {reinterpret_cast<const void*>(&de::k_comp_eval),
+                         reinterpret_cast<const void*>(&de::k_sur_select),
+                         reinterpret_cast<const void*>(&de::k_mlp_infer),
+                         reinterpret_cast<const void*>(&de::k_train_fwd)};
+    // dynamic LDS may use what the kernel's static LDS leaves free
+    for (const void* f : fns) {
+      hipFuncAttributes fa{};
+      if (err == hipSuccess) err = hipFuncGetAttributes(&fa, f);
+      if (err == hipSuccess)
+        err = hipFuncSetAttribute(
+            f, hipFuncAttributeMaxDynamicSharedMemorySize,
+            de::kMaxLdsBytes - (int)fa.sharedSizeBytes);
+    }
+  });
+  return from_hip(err);
+}
+
+de_status prep_model(de_sur* s, hipStream_t st) {
+  const SurArgs a = args_of(s);
+  const size_t work = (size_t)a.runs *
+                      ((size_t)a.H * a.Dp + (size_t)a.H * a.H);
+  hipLaunchKernelGGL(de::k_model_prep, dim3(grid_for(work, 256)), dim3(256), 0,
+                     st, a);
+  return from_hip(hipGetLastError());
+}
+
+de_status train_steps(de_sur* s, int n, hipStream_t st) {
+  const int P = (int)model_size(s->p.D, s->sp.hidden);
+  for (int k = 0; k < n; ++k) {
+    s->step += 1;
+    SurArgs a = args_of(s);
+    a.c1 = (float)(1.0 - std::pow((double)s->sp.beta1, (double)s->step));
+    a.c2 = (float)(1.0 - std::pow((double)s->sp.beta2, (double)s->step));
+    const size_t lds = de::train_lds_floats(a.D, a.H) * 4;
+    hipLaunchKernelGGL(de::k_train_fwd, dim3(a.B / de::kTrainRows, a.runs),
+                       dim3(256), lds, st, a);
+    de_status rc = from_hip(hipGetLastError());
+    if (rc != DE_OK) return rc;
+    hipLaunchKernelGGL(de::k_train_adam,
+                       dim3(grid_for((size_t)a.runs * P, 256)), dim3(256), 0,
+                       st, a, P);
+    rc = from_hip(hipGetLastError());
+    if (rc != DE_OK) return rc;
+    rc = prep_model(s, st);
+    if (rc != DE_OK) return rc;
+  }
+  return DE_OK;
+}
+
+de_status comp_eval(const de_sur* s, const float* X, int n, int ldx, float* f,
+                    hipStream_t st) {
+  if (n == 0) return DE_OK;
+  const SurArgs a = args_of(s);
+  const size_t lds = de::comp_lds_floats(a.D) * 4;
+  hipLaunchKernelGGL(de::k_comp_eval,
+                     dim3((n + de::kEvalRows - 1) / de::kEvalRows),
+                     dim3(de::kEvalThreads), lds, st, a, X, n, ldx, f);
+  return from_hip(hipGetLastError());
+}
+
+de_status one_generation(de_sur* s, hipStream_t st) {
+  SurArgs a = args_of(s);
+  a.use_model = (s->sp.k > 1 && s->gen >= s->sp.warmup_gens) ? 1 : 0;
+  s->last_use_model = a.use_model;
+  hipLaunchKernelGGL(de::k_sur_cand, dim3((a.NP * a.k + 3) / 4, a.runs),
+                     dim3(256), 0, st, a);
+  de_status rc = from_hip(hipGetLastError());
+  if (rc != DE_OK) return rc;
+  if (a.use_model) {
+    const int rows = a.NP * a.k;
+    hipLaunchKernelGGL(de::k_mlp_infer,
+                       dim3((rows + de::kInferRows - 1) / de::kInferRows,
+                            a.runs),
+                       dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a,
+                       (const float*)a.cand, (size_t)rows * a.ldx, rows, a.ldx,
+                       a.pred, (size_t)rows, 0);
+    rc = from_hip(hipGetLastError());
+    if (rc != DE_OK) return rc;
+  } else {
+    rc = from_hip(hipMemsetAsync(a.pred, 0,
+                                 4 * (size_t)a.runs * a.NP * a.k, st));
+    if (rc != DE_OK) return rc;
+  }
+  hipLaunchKernelGGL(de::k_sur_select,
+                     dim3((a.NP + de::kEvalRows - 1) / de::kEvalRows, a.runs),
+                     dim3(de::kEvalThreads), de::comp_lds_floats(a.D) * 4, st,
+                     a);
+  rc = from_hip(hipGetLastError());
+  if (rc != DE_OK) return rc;
+  s->gen += 1;
+  s->rounds += 1;
+  return train_steps(s, s->sp.steps, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+DE_API int64_t de_sur_model_size(int32_t D, int32_t hidden) {
+  if (D < 1 || hidden < 1) return 0;
+  return model_size(D, hidden);
+}
+
+DE_API de_status de_sur_workspace_bytes(const de_params* params,
+                                        const de_composition* comp,
+                                        const de_surrogate_params* sp,
+                                        size_t* bytes) {
+  if (!bytes) return DE_E_INVAL;
+  const de_status rc = check(params, comp, sp);
+  if (rc != DE_OK) return rc;
+  // the caller's ldx is not known here: rows are sized for D rounded to 4
+  *bytes = layout(*params, *comp, *sp, (int)rup(params->D, 4)).total;
+  return DE_OK;
+}
+
+DE_API de_status de_sur_init(const de_params* params,
+                             const de_composition* comp,
+                             const de_surrogate_params* sp,
+                             const de_buffers* buffers, void* hip_stream,
+                             de_sur** out) {
+  if (!out || !buffers) return DE_E_INVAL;
+  *out = nullptr;
+  de_status rc = check(params, comp, sp);
+  if (rc != DE_OK) return rc;
+  const de_params& p = *params;
+  if (buffers->reserved != 0) return DE_E_INVAL;
+  if (buffers->ldx != (int32_t)rup(p.D, 4)) return DE_E_INVAL;
+  for (int b = 0; b < 2; ++b) {
+    if (!buffers->pop[b] || !buffers->fit[b]) return DE_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(buffers->pop[b]) % 16 ||
+        reinterpret_cast<uintptr_t>(buffers->fit[b]) % 4)
+      return DE_E_INVAL;
+  }
+  if (buffers->pop[0] == buffers->pop[1] || buffers->fit[0] == buffers->fit[1])
+    return DE_E_INVAL;
+  const SLayout L = layout(p, *comp, *sp, buffers->ldx);
+  if (!buffers->work || reinterpret_cast<uintptr_t>(buffers->work) % 256 ||
+      buffers->work_bytes < L.total)
+    return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  rc = set_lds_attributes();
+  if (rc != DE_OK) return rc;
+  de_sur* s = new (std::nothrow) de_sur();
+  if (!s) return DE_E_NOMEM;
+  s->p = p;
+  s->sp = *sp;
+  s->n = comp->n;
+  s->sigma = comp->sigma;
+  s->ldx = buffers->ldx;
+  for (int b = 0; b < 2; ++b) {
+    s->pop[b] = buffers->pop[b];
+    s->fit[b] = buffers->fit[b];
+  }
+  s->work = static_cast<char*>(buffers->work);
+  s->L = L;
+  auto fail = [&](de_status e) {
+    delete s;
+    return e;
+  };
+  SurArgs a = args_of(s);
+  // composition data
+  hipLaunchKernelGGL(de::k_comp_prep,
+                     dim3(grid_for((size_t)comp->n * p.D * p.D, 256)),
+                     dim3(256), 0, st, comp->O, comp->R, comp->ldr, comp->n,
+                     p.D, const_cast<float*>(a.O), const_cast<float*>(a.Rt));
+  rc = from_hip(hipGetLastError());
+  if (rc == DE_OK)
+    rc = from_hip(hipMemcpyAsync(const_cast<float*>(a.bias), comp->bias,
+                                 4 * (size_t)comp->n, hipMemcpyHostToDevice,
+                                 st));
+  // generation 0 (the per-problem initialisation kernel, same draws)
+  if (rc == DE_OK) {
+    de::GenArgs g{};
+    g.pop_next = s->pop[0];
+    g.runs = p.runs;
+    g.NP = p.NP;
+    g.D = p.D;
+    g.ldx = s->ldx;
+    g.nrows = p.runs * p.NP;
+    g.lo = p.lo;
+    g.hi = p.hi;
+    g.key_lo = (uint32_t)p.seed;
+    g.key_hi = (uint32_t)(p.seed >> 32);
+    rc = from_hip(de::launch_init(g, st));
+  }
+  if (rc == DE_OK)
+    rc = comp_eval(s, s->pop[0], p.runs * p.NP, s->ldx, s->fit[0], st);
+  if (rc == DE_OK) {
+    hipLaunchKernelGGL(de::k_archive_init,
+                       dim3(grid_for((size_t)p.runs * p.NP * ((p.D + 3) / 4),
+                                     256)),
+                       dim3(256), 0, st, a);
+    rc = from_hip(hipGetLastError());
+  }
+  if (rc == DE_OK) {
+    hipLaunchKernelGGL(de::k_sur_reset, dim3(grid_for(p.runs, 256)),
+                       dim3(256), 0, st, a);
+    rc = from_hip(hipGetLastError());
+  }
+  if (rc == DE_OK) {
+    hipLaunchKernelGGL(de::k_sur_best, dim3(p.runs), dim3(256), 0, st, a);
+    rc = from_hip(hipGetLastError());
+  }
+  if (rc == DE_OK) {
+    const int P = (int)model_size(p.D, sp->hidden);
+    hipLaunchKernelGGL(de::k_model_init,
+                       dim3(grid_for((size_t)p.runs * L.pstride, 256)),
+                       dim3(256), 0, st, a, P);
+    rc = from_hip(hipGetLastError());
+  }
+  if (rc == DE_OK) rc = prep_model(s, st);
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc != DE_OK) return fail(rc);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    live_set().insert(s);
+  }
+  *out = s;
+  return DE_OK;
+}
+
+DE_API de_status de_sur_generation(de_sur* s, int32_t n_gens,
+                                   void* hip_stream) {
+  if (!live(s)) return DE_E_STATE;
+  if (n_gens < 0) return DE_E_INVAL;
+  if (s->gen + n_gens >= ((int64_t)1 << 32)) return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int g = 0; g < n_gens; ++g) {
+    const de_status rc = one_generation(s, st);
+    if (rc != DE_OK) return rc;
+  }
+  return DE_OK;
+}
+
+DE_API de_status de_sur_read(de_sur* s, void* hip_stream, double* best_f,
+                             int32_t* best_idx, int64_t* accepted) {
+  if (!live(s)) return DE_E_STATE;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t n = (size_t)s->p.runs;
+  std::vector<unsigned long long> key(n), acc(n);
+  de_status rc = from_hip(hipMemcpyAsync(key.data(), s->work + s->L.best,
+                                         8 * n, hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK)
+    rc = from_hip(hipMemcpyAsync(acc.data(), s->work + s->L.acc, 8 * n,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc != DE_OK) return rc;
+  for (size_t r = 0; r < n; ++r) {
+    const uint32_t ord = (uint32_t)(key[r] >> 32);
+    const uint32_t bits = (ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord;
+    float f;
+    std::memcpy(&f, &bits, 4);
+    if (best_f) best_f[r] = (double)f;
+    if (best_idx) best_idx[r] = (int32_t)(uint32_t)key[r];
+    if (accepted) accepted[r] = (int64_t)acc[r];
+  }
+  return DE_OK;
+}
+
+DE_API de_status de_sur_get_generation(const de_sur* s, int64_t* gen) {
+  if (!live(s)) return DE_E_STATE;
+  if (!gen) return DE_E_INVAL;
+  *gen = s->gen;
+  return DE_OK;
+}
+
+DE_API de_status de_sur_eval(de_sur* s, const float* x_dev, int32_t n,
+                             int32_t ldx, float* f_dev, void* hip_stream) {
+  if (!live(s)) return DE_E_STATE;
+  if (n < 0 || (n > 0 && (!x_dev || !f_dev)) || ldx < s->p.D || ldx % 4)
+    return DE_E_INVAL;
+  (void)hipGetLastError();
+  return comp_eval(s, x_dev, n, ldx, f_dev,
+                   reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+DE_API de_status de_sur_predict(de_sur* s, int32_t run, const float* x_dev,
+                                int32_t n, int32_t ldx, float* y_dev,
+                                void* hip_stream) {
+  if (!live(s)) return DE_E_STATE;
+  if (run < 0 || run >= s->p.runs || n < 0 || ldx < s->p.D ||
+      (n > 0 && (!x_dev || !y_dev)))
+    return DE_E_INVAL;
+  if (n == 0) return DE_OK;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const SurArgs a = args_of(s);
+  hipLaunchKernelGGL(de::k_mlp_infer,
+                     dim3((n + de::kInferRows - 1) / de::kInferRows, 1),
+                     dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a, x_dev,
+                     (size_t)0, n, ldx, y_dev, (size_t)0, run);
+  return from_hip(hipGetLastError());
+}
+
+DE_API de_status de_sur_get_model(de_sur* s, void* hip_stream, float* theta,
+                                  float* m, float* v, int64_t* step) {
+  if (!live(s)) return DE_E_STATE;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t P = (size_t)model_size(s->p.D, s->sp.hidden);
+  float* dst[3] = {theta, m, v};
+  const size_t src[3] = {s->L.theta, s->L.m, s->L.v};
+  de_status rc = DE_OK;
+  for (int q = 0; q < 3 && rc == DE_OK; ++q) {
+    if (!dst[q]) continue;
+    for (int r = 0; r < s->p.runs && rc == DE_OK; ++r)
+      rc = from_hip(hipMemcpyAsync(
+          dst[q] + (size_t)r * P,
+          s->work + src[q] + 4 * (size_t)r * s->L.pstride, 4 * P,
+          hipMemcpyDeviceToHost, st));
+  }
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK && step) *step = s->step;
+  return rc;
+}
+
+DE_API de_status de_sur_set_model(de_sur* s, void* hip_stream,
+                                  const float* theta, const float* m,
+                                  const float* v, int64_t step) {
+  if (!live(s)) return DE_E_STATE;
+  if (!theta || !m || !v || step < 0 || step >= ((int64_t)1 << 32))
+    return DE_E_INVAL;
+  const size_t P = (size_t)model_size(s->p.D, s->sp.hidden);
+  const size_t n = P * s->p.runs;
+  for (size_t t = 0; t < n; ++t)
+    if (!std::isfinite(theta[t]) || !std::isfinite(m[t]) ||
+        !std::isfinite(v[t]) || v[t] < 0.f)
+      return DE_E_INVAL;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const float* srcs[3] = {theta, m, v};
+  const size_t dst[3] = {s->L.theta, s->L.m, s->L.v};
+  de_status rc = DE_OK;
+  for (int q = 0; q < 3 && rc == DE_OK; ++q)
+    for (int r = 0; r < s->p.runs && rc == DE_OK; ++r)
+      rc = from_hip(hipMemcpyAsync(
+          s->work + dst[q] + 4 * (size_t)r * s->L.pstride,
+          srcs[q] + (size_t)r * P, 4 * P, hipMemcpyHostToDevice, st));
+  if (rc == DE_OK) rc = prep_model(s, st);
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) s->step = step;
+  return rc;
+}
+
+DE_API de_status de_sur_train(de_sur* s, int32_t n_steps, void* hip_stream) {
+  if (!live(s)) return DE_E_STATE;
+  if (n_steps < 0) return DE_E_INVAL;
+  (void)hipGetLastError();
+  return train_steps(s, n_steps, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+DE_API de_status de_sur_get_archive(de_sur* s, void* hip_stream, float* X,
+                                    float* T, int64_t* filled) {
+  if (!live(s)) return DE_E_STATE;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t cap = (size_t)s->sp.archive, R = (size_t)s->p.runs;
+  de_status rc = DE_OK;
+  if (X)
+    rc = from_hip(hipMemcpy2DAsync(X, 4 * (size_t)s->p.D, s->work + s->L.ax,
+                                   4 * (size_t)s->ldx, 4 * (size_t)s->p.D,
+                                   R * cap, hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK && T)
+    rc = from_hip(hipMemcpyAsync(T, s->work + s->L.at, 4 * R * cap,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK && filled)
+    for (size_t r = 0; r < R; ++r)
+      filled[r] = std::min<int64_t>(s->sp.archive, s->rounds * s->p.NP);
+  return rc;
+}
+
+DE_API de_status de_sur_last(de_sur* s, void* hip_stream, float* cand,
+                             float* pred, int32_t* choice) {
+  if (!live(s)) return DE_E_STATE;
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t R = (size_t)s->p.runs, NP = (size_t)s->p.NP,
+               k = (size_t)s->sp.k;
+  de_status rc = DE_OK;
+  if (cand)
+    rc = from_hip(hipMemcpy2DAsync(cand, 4 * (size_t)s->p.D,
+                                   s->work + s->L.cand, 4 * (size_t)s->ldx,
+                                   4 * (size_t)s->p.D, R * NP * k,
+                                   hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK && pred)
+    rc = from_hip(hipMemcpyAsync(pred, s->work + s->L.pred, 4 * R * NP * k,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK && choice)
+    rc = from_hip(hipMemcpyAsync(choice, s->work + s->L.choice, 4 * R * NP,
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  return rc;
+}
+
+DE_API de_status de_sur_destroy(de_sur* s) {
+  if (!live(s)) return DE_E_STATE;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    live_set().erase(s);
+  }
+  s->magic = 0;
+  delete s;
+  return DE_OK;
+}
+
+}  // extern "C"

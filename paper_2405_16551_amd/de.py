@@ -53,6 +53,27 @@ class de_jde(ctypes.Structure):
 JDE_BREST = dict(F_lo=0.1, F_span=0.9, tau_F=0.1, tau_CR=0.1)
 
 
+class de_composition(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ldr", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("O", ctypes.c_void_p), ("R", ctypes.c_void_p),
+                ("bias", ctypes.POINTER(ctypes.c_float))]
+
+
+class de_surrogate_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("archive", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("warmup_gens", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("model_seed", ctypes.c_uint64)]
+
+
+SURROGATE_DEFAULTS = dict(k=4, hidden=256, archive=8192, batch=256, steps=2,
+                          warmup_gens=5, lr=1e-3, beta1=0.9, beta2=0.999,
+                          eps=1e-8, model_seed=7)
+
+
 class de_run_spec(ctypes.Structure):
     _fields_ = [("NP", ctypes.c_int32), ("D", ctypes.c_int32),
                 ("F", ctypes.c_float), ("CR", ctypes.c_float)]
@@ -82,6 +103,12 @@ EXPORTS = ("de_abi_version", "de_strerror", "de_workspace_bytes",
            "de_best_f64", "de_get_generation", "de_read_stats", "de_load_population",
            "de_eval", "de_debug_draws", "de_destroy",
            "de_init_population_jde", "de_get_control", "de_set_control",
+           # include/de_surrogate.h
+           "de_sur_model_size", "de_sur_workspace_bytes", "de_sur_init",
+           "de_sur_generation", "de_sur_read", "de_sur_get_generation",
+           "de_sur_eval", "de_sur_predict", "de_sur_get_model",
+           "de_sur_set_model", "de_sur_train", "de_sur_get_archive",
+           "de_sur_last", "de_sur_destroy",
            # include/de_batch.h
            "de_batch_layout", "de_batch_create", "de_batch_plan",
            "de_batch_generation", "de_batch_read", "de_batch_get_generation",
@@ -139,6 +166,38 @@ def _load():
     lib.de_destroy.restype = st
     lib.de_destroy.argtypes = [vp]
     szp = P(ctypes.c_size_t)
+    fpp = P(ctypes.c_float)
+    lib.de_sur_model_size.restype = i64
+    lib.de_sur_model_size.argtypes = [i32, i32]
+    lib.de_sur_workspace_bytes.restype = st
+    lib.de_sur_workspace_bytes.argtypes = [P(de_params), P(de_composition),
+                                           P(de_surrogate_params), szp]
+    lib.de_sur_init.restype = st
+    lib.de_sur_init.argtypes = [P(de_params), P(de_composition),
+                                P(de_surrogate_params), P(de_buffers), vp,
+                                P(vp)]
+    lib.de_sur_generation.restype = st
+    lib.de_sur_generation.argtypes = [vp, i32, vp]
+    lib.de_sur_read.restype = st
+    lib.de_sur_read.argtypes = [vp, vp, P(ctypes.c_double), P(i32), P(i64)]
+    lib.de_sur_get_generation.restype = st
+    lib.de_sur_get_generation.argtypes = [vp, P(i64)]
+    lib.de_sur_eval.restype = st
+    lib.de_sur_eval.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.de_sur_predict.restype = st
+    lib.de_sur_predict.argtypes = [vp, i32, vp, i32, i32, vp, vp]
+    lib.de_sur_get_model.restype = st
+    lib.de_sur_get_model.argtypes = [vp, vp, fpp, fpp, fpp, P(i64)]
+    lib.de_sur_set_model.restype = st
+    lib.de_sur_set_model.argtypes = [vp, vp, fpp, fpp, fpp, i64]
+    lib.de_sur_train.restype = st
+    lib.de_sur_train.argtypes = [vp, i32, vp]
+    lib.de_sur_get_archive.restype = st
+    lib.de_sur_get_archive.argtypes = [vp, vp, fpp, fpp, P(i64)]
+    lib.de_sur_last.restype = st
+    lib.de_sur_last.argtypes = [vp, vp, fpp, fpp, P(i32)]
+    lib.de_sur_destroy.restype = st
+    lib.de_sur_destroy.argtypes = [vp]
     lib.de_batch_layout.restype = st
     lib.de_batch_layout.argtypes = [P(de_batch_params), P(i64), P(i32), P(i64),
                                     szp, szp, szp]
@@ -573,3 +632,178 @@ class DEBatch:
         g = self.gen if gen is None else gen
         off = self.layout["fit_off"][run]
         return self.fit[g & 1][off:off + self.specs[run][0]]
+
+
+class SurrogateDE:
+    """Surrogate-assisted DE on a composition objective (de_surrogate.h).
+
+    ``comp``: (O [n, D], R [n, D, D], bias [n], sigma).  ``settings``:
+    overrides of SURROGATE_DEFAULTS.  Populations are views as in
+    DifferentialEvolution; the model state is read and written as NumPy.
+    """
+
+    def __init__(self, *, runs, NP, D, F, CR, comp, lo=-100.0, hi=100.0,
+                 seed=1, device="cuda", stream=None, **settings):
+        import numpy as np
+        import torch
+        self.torch, self.np = torch, np
+        self.runs, self.NP, self.D = int(runs), int(NP), int(D)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ldx = (self.D + 3) // 4 * 4
+        O, R, bias, sigma = comp
+        dev = self.device
+        self._O = torch.as_tensor(np.asarray(O, np.float32)).to(dev).contiguous()
+        self._R = torch.as_tensor(np.asarray(R, np.float32)).to(dev).contiguous()
+        self._bias = (ctypes.c_float * len(bias))(*[float(b) for b in bias])
+        self.comp = de_composition(len(bias), self.D, float(sigma), 0,
+                                   self._O.data_ptr(), self._R.data_ptr(),
+                                   self._bias)
+        cfg = dict(SURROGATE_DEFAULTS)
+        cfg.update(settings)
+        self.cfg = cfg
+        self.sp = de_surrogate_params(*[cfg[f] for f, _ in de_surrogate_params._fields_])
+        self.params = de_params(self.runs, self.NP, self.D, float(F), float(CR),
+                                float(lo), float(hi), int(seed))
+        wb = ctypes.c_size_t()
+        _check(_lib.de_sur_workspace_bytes(ctypes.byref(self.params),
+                                           ctypes.byref(self.comp),
+                                           ctypes.byref(self.sp),
+                                           ctypes.byref(wb)),
+               "de_sur_workspace_bytes")
+        rows = self.runs * self.NP
+        self.pop = [torch.zeros(rows * self.ldx, dtype=torch.float32, device=dev)
+                    for _ in range(2)]
+        self.fit = [torch.zeros(rows, dtype=torch.float32, device=dev)
+                    for _ in range(2)]
+        self.work = torch.zeros(wb.value + 256, dtype=torch.uint8, device=dev)
+        wptr = (self.work.data_ptr() + 255) // 256 * 256
+        self.buffers = de_buffers(
+            (ctypes.c_void_p * 2)(self.pop[0].data_ptr(), self.pop[1].data_ptr()),
+            (ctypes.c_void_p * 2)(self.fit[0].data_ptr(), self.fit[1].data_ptr()),
+            self.ldx, 0, wptr, wb.value)
+        h = ctypes.c_void_p()
+        _check(_lib.de_sur_init(ctypes.byref(self.params),
+                                ctypes.byref(self.comp), ctypes.byref(self.sp),
+                                ctypes.byref(self.buffers), self._s(),
+                                ctypes.byref(h)), "de_sur_init")
+        self.handle = h
+        self.P = int(_lib.de_sur_model_size(self.D, cfg["hidden"]))
+
+    def _s(self):
+        return self.stream.cuda_stream
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _check(_lib.de_sur_destroy(self.handle), "de_sur_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def gen(self) -> int:
+        g = ctypes.c_int64()
+        _check(_lib.de_sur_get_generation(self.handle, ctypes.byref(g)),
+               "de_sur_get_generation")
+        return int(g.value)
+
+    def generation(self, n: int = 1):
+        _check(_lib.de_sur_generation(self.handle, n, self._s()),
+               "de_sur_generation")
+
+    def train(self, n: int = 1):
+        _check(_lib.de_sur_train(self.handle, n, self._s()), "de_sur_train")
+
+    def read(self):
+        n = self.runs
+        best = (ctypes.c_double * n)()
+        idx = (ctypes.c_int32 * n)()
+        acc = (ctypes.c_int64 * n)()
+        _check(_lib.de_sur_read(self.handle, self._s(), best, idx, acc),
+               "de_sur_read")
+        return dict(best_f=list(best), best_idx=list(idx), accepted=list(acc))
+
+    def population(self, gen=None):
+        g = self.gen if gen is None else gen
+        return self.pop[g & 1].view(self.runs, self.NP, self.ldx)[:, :, :self.D]
+
+    def fitness(self, gen=None):
+        g = self.gen if gen is None else gen
+        return self.fit[g & 1].view(self.runs, self.NP)
+
+    def _rows(self, x):
+        torch = self.torch
+        x = torch.as_tensor(x, dtype=torch.float32).to(self.device)
+        xp = torch.zeros((x.shape[0], self.ldx), dtype=torch.float32,
+                         device=self.device)
+        xp[:, :self.D] = x
+        return xp
+
+    def eval(self, x):
+        xp = self._rows(x)
+        f = self.torch.empty(xp.shape[0], dtype=self.torch.float32,
+                             device=self.device)
+        _check(_lib.de_sur_eval(self.handle, xp.data_ptr(), xp.shape[0],
+                                self.ldx, f.data_ptr(), self._s()),
+               "de_sur_eval")
+        return f
+
+    def predict(self, run, x):
+        xp = self._rows(x)
+        y = self.torch.empty(xp.shape[0], dtype=self.torch.float32,
+                             device=self.device)
+        _check(_lib.de_sur_predict(self.handle, run, xp.data_ptr(),
+                                   xp.shape[0], self.ldx, y.data_ptr(),
+                                   self._s()), "de_sur_predict")
+        return y
+
+    def get_model(self):
+        np = self.np
+        n = self.runs * self.P
+        th, m, v = (np.empty(n, np.float32) for _ in range(3))
+        step = ctypes.c_int64()
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(_lib.de_sur_get_model(self.handle, self._s(),
+                                     th.ctypes.data_as(fp), m.ctypes.data_as(fp),
+                                     v.ctypes.data_as(fp), ctypes.byref(step)),
+               "de_sur_get_model")
+        shp = (self.runs, self.P)
+        return th.reshape(shp), m.reshape(shp), v.reshape(shp), int(step.value)
+
+    def set_model(self, theta, m, v, step):
+        np = self.np
+        fp = ctypes.POINTER(ctypes.c_float)
+        arrs = [np.ascontiguousarray(a, np.float32).ravel() for a in (theta, m, v)]
+        _check(_lib.de_sur_set_model(self.handle, self._s(),
+                                     *[a.ctypes.data_as(fp) for a in arrs],
+                                     int(step)), "de_sur_set_model")
+
+    def archive(self):
+        np = self.np
+        cap = self.cfg["archive"]
+        X = np.empty((self.runs, cap, self.D), np.float32)
+        T = np.empty((self.runs, cap), np.float32)
+        filled = (ctypes.c_int64 * self.runs)()
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(_lib.de_sur_get_archive(self.handle, self._s(),
+                                       X.ctypes.data_as(fp),
+                                       T.ctypes.data_as(fp), filled),
+               "de_sur_get_archive")
+        return X, T, list(filled)
+
+    def last(self):
+        np = self.np
+        k = self.cfg["k"]
+        cand = np.empty((self.runs, self.NP, k, self.D), np.float32)
+        pred = np.empty((self.runs, self.NP, k), np.float32)
+        choice = np.empty((self.runs, self.NP), np.int32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(_lib.de_sur_last(self.handle, self._s(), cand.ctypes.data_as(fp),
+                                pred.ctypes.data_as(fp),
+                                choice.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+               "de_sur_last")
+        return cand, pred, choice
