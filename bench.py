@@ -223,6 +223,66 @@ def time_batch(steps, warmup, nruns=MIXED_RUNS, graph_gens=MIXED_GRAPH_GENS):
         create_s=round(create_s, 3))
 
 
+SUR_RUNS = 30
+
+
+def describe_surrogate(runs=SUR_RUNS):
+    return (f"surrogate-assisted DE/rand/1/bin, {runs} runs x NP=512, D=100, "
+            "composition of 8 rotated oscillating components (weights "
+            "exp(-d/(2*50^2)), biases 100k), F=0.5, CR=0.9; BF16 MLP "
+            "100-256-256-1 trained online (Adam, minibatch 256, 1 step per "
+            "generation, archive 16384), k=4 candidates per target, "
+            "1 true evaluation")
+
+
+def time_surrogate(gens=300, check_every=10, runs=SUR_RUNS):
+    """Plain form (k = 1, no model, same kernels) for `gens` generations,
+    then the surrogate form until its median best reaches the plain form's
+    final median best (or 2 * gens generations); wall-clock both."""
+    import numpy as np
+    import torch
+
+    from paper_2405_16551_amd import instances
+    from paper_2405_16551_amd.de import SurrogateDE
+
+    comp = instances.make_composition(100, 8, 1)
+    common = dict(runs=runs, NP=512, D=100, F=0.5, CR=0.9, comp=comp, seed=1,
+                  hidden=256, batch=256, archive=16384)
+    plain = SurrogateDE(k=1, steps=0, warmup_gens=0, **common)
+    sur = SurrogateDE(k=4, steps=1, warmup_gens=5, **common)
+    torch.cuda.synchronize()
+
+    def run(s, stop):
+        t0 = time.perf_counter()
+        done = 0
+        trace = []
+        while done < stop[0]:
+            s.generation(check_every)
+            done += check_every
+            med = float(np.median(s.read()["best_f"]))
+            trace.append((done, med))
+            if stop[1] is not None and med <= stop[1]:
+                break
+        return time.perf_counter() - t0, done, trace
+
+    tp, gp, trp = run(plain, (gens, None))
+    target = trp[-1][1]
+    ts, gs, trs = run(sur, (2 * gens, target))
+    reached = trs[-1][1] <= target
+    plain.close()
+    sur.close()
+    return dict(
+        workload=describe_surrogate(runs), runs=runs,
+        plain=dict(generations=gp, seconds=round(tp, 3),
+                   ms_per_gen=round(tp / gp * 1e3, 4),
+                   median_best=target),
+        surrogate=dict(generations=gs, seconds=round(ts, 3),
+                       ms_per_gen=round(ts / gs * 1e3, 4),
+                       median_best=trs[-1][1], reached_plain_best=reached),
+        speedup_to_same_best=round(tp / ts, 3) if reached else None,
+        true_evals_ratio=round(gs / gp, 3))
+
+
 def copy_ceiling(nbytes=1 << 30, reps=20):
     """Device-to-device copy of nbytes (read + write), timed with events:
     the measured HBM ceiling next to the 8 TB/s specification."""
@@ -303,7 +363,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot1000_bf16",
-                    choices=sorted(WORKLOADS) + ["mixed512"])
+                    choices=sorted(WORKLOADS) + ["mixed512", "surrogate"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -320,6 +380,11 @@ def main():
 
     if args.copy_calibration:
         copy_ceiling(nbytes=256 << 20, reps=1)
+    if args.workload == "surrogate":
+        r = time_surrogate()
+        print(json.dumps({"metric": "wall-time to the plain form's best",
+                          "n_gpus": 1, "data": "synthetic", **r}), flush=True)
+        return
     if args.workload == "mixed512":
         r = time_batch(args.steps, args.warmup)
         print(json.dumps({
@@ -375,6 +440,7 @@ def main():
             "kernel_ms_per_step": round(j["kernel_ms"], 5),
             "accept_rate": j["accept_rate"], "roofline": j["roofline"]}
         line["batched"] = time_batch(max(64, args.steps // 4), args.warmup)
+        line["surrogate"] = time_surrogate()
         line["time_to_target"] = time_to_target()
         line["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:

@@ -58,7 +58,7 @@ typedef struct de_composition {
  *   k           candidates per target, 1..16
  *   hidden      H, a multiple of 32 in 32..256
  *   archive     archive rows per run, >= max(batch, NP)
- *   batch       minibatch rows, a multiple of 16 in 16..1024
+ *   batch       minibatch rows, a multiple of 32 in 32..1024
  *   steps       Adam steps per generation, >= 0
  *   warmup_gens generations before the model screens candidates, >= 0
  *   lr, beta1, beta2, eps   Adam (finite; lr > 0, betas in [0, 1), eps > 0)

@@ -13,12 +13,15 @@
 //                  generation, statistics, archive insert
 // then `steps` Adam steps of every run's model (FP32):
 //   k_train_fwd    minibatch rows drawn from the archive, forward pass,
-//                  output error and both hidden-layer deltas (16 rows per
-//                  workgroup, one thread per hidden unit)
-//   k_train_adam   one thread per parameter: its gradient summed over the
-//                  minibatch in row order, then the Adam update
-//   k_model_prep   BF16 fragment copies for inference and FP32 transposed
-//                  copies for the next forward pass
+//                  output error and both hidden-layer deltas, FP32 MFMA
+//                  (32 rows per workgroup)
+//   k_train_grad   weight gradients as FP32 MFMA products over the
+//                  minibatch (one wave per 32x32 block), bias gradients
+//                  from eight partial row sums, then the Adam update per
+//                  entry, which also refreshes the BF16 fragment copy used
+//                  for inference and the FP32 transposed copy used by the
+//                  next forward pass (k_model_prep builds both after
+//                  initialisation and when the model is set)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -241,6 +244,30 @@ __host__ __device__ constexpr size_t infer_lds_bytes(int Dp, int H) {
          (size_t)kInferRows * H * 4;
 }
 
+// One 32x32 BF16 block over kbn K-steps of 16 (kbn even): A fragments
+// from LDS at ar + 16 kb, B fragments at wf[kb * 64]; two K-steps per batch,
+// each batch's reads issued one batch ahead.
+__device__ __forceinline__ floatx16 mfma_bf16_block(const __bf16* ar,
+                                                    const bf16x8* wf,
+                                                    int kbn) {
+  floatx16 c = {};
+  bf16x8 an0 = *reinterpret_cast<const bf16x8*>(ar);
+  bf16x8 an1 = *reinterpret_cast<const bf16x8*>(ar + 16);
+  bf16x8 bn0 = wf[0], bn1 = wf[64];
+  for (int kb = 0; kb < kbn; kb += 2) {
+    const bf16x8 a0 = an0, a1 = an1, b0 = bn0, b1 = bn1;
+    if (kb + 2 < kbn) {
+      an0 = *reinterpret_cast<const bf16x8*>(ar + 16 * (kb + 2));
+      an1 = *reinterpret_cast<const bf16x8*>(ar + 16 * (kb + 3));
+      bn0 = wf[(size_t)(kb + 2) * 64];
+      bn1 = wf[(size_t)(kb + 3) * 64];
+    }
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, c, 0, 0, 0);
+  }
+  return c;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
                                                    size_t x_run_stride, int n,
                                                    int ldx, float* y,
@@ -277,12 +304,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
                        (size_t)run * nblk * kbn * 64;
     const __bf16* ar = A + (size_t)(lane % 32) * sa + 8 * (lane / 32);
     for (int nb = wave; nb < nblk; nb += 4) {
-      floatx16 c = {};
-      for (int kb = 0; kb < kbn; ++kb) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(ar + 16 * kb);
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            av, wf[((size_t)nb * kbn + kb) * 64 + lane], c, 0, 0, 0);
-      }
+      const floatx16 c =
+          mfma_bf16_block(ar, wf + (size_t)nb * kbn * 64 + lane, kbn);
       const int col = nb * 32 + lane % 32;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -299,12 +322,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
                        (size_t)run * nblk * kbn * 64;
     const __bf16* ar = H1 + (size_t)(lane % 32) * sh + 8 * (lane / 32);
     for (int nb = wave; nb < nblk; nb += 4) {
-      floatx16 c = {};
-      for (int kb = 0; kb < kbn; ++kb) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(ar + 16 * kb);
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            av, wf[((size_t)nb * kbn + kb) * 64 + lane], c, 0, 0, 0);
-      }
+      const floatx16 c =
+          mfma_bf16_block(ar, wf + (size_t)nb * kbn * 64 + lane, kbn);
       const int col = nb * 32 + lane % 32;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -466,27 +485,75 @@ __global__ __launch_bounds__(256) void k_model_prep(SurArgs a) {
   }
 }
 
-constexpr int kTrainRows = 16;
+// Training on FP32 MFMA (32x32x2, lane l supplies A(l % 32, 2 kb + l / 32)
+// and B(2 kb + l / 32, l % 32); register r of lane l holds C(8 (r / 4) +
+// 4 (l / 32) + r % 4, l % 32)).  Minibatch rows in blocks of 32.
+constexpr int kTrainRows = 32;
 
-__host__ __device__ constexpr size_t train_lds_floats(int D, int H) {
-  return (size_t)kTrainRows * D + (size_t)3 * kTrainRows * H + 2 * kTrainRows;
+__host__ __device__ constexpr size_t train_lds_floats(int Dp, int H) {
+  return (size_t)kTrainRows * (Dp + 1) + (size_t)3 * kTrainRows * (H + 1) +
+         2 * kTrainRows;
 }
 
-// Forward pass of 16 minibatch rows per workgroup (one thread per hidden
-// unit, H <= 256), output error e = 2 (y - t) / B and the deltas of both
-// hidden layers; everything the gradient needs goes to the scratch arrays.
-__global__ __launch_bounds__(256) void k_train_fwd(SurArgs a) {
+__device__ __forceinline__ int c_row(int r, int lane) {
+  return 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+}
+
+// One 32x32 block C = A B over K (a multiple of 16): the lane's A values
+// at ap[2 kb * astep], its B values at bp[2 kb * bstep] (rows k >= kvalid
+// of B read as zero).  K-steps go in batches of eight whose loads are
+// issued one batch ahead of the MFMAs that use them.
+__device__ __forceinline__ floatx16 mfma_block(const float* ap, int astep,
+                                               const float* bp, int bstep,
+                                               int K, int kvalid, int lk) {
+  floatx16 c = {};
+  float an[8], bn[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    an[u] = ap[(size_t)2 * u * astep];
+    bn[u] = 2 * u + lk < kvalid ? bp[(size_t)2 * u * bstep] : 0.f;
+  }
+  for (int kb = 0; kb < K / 2; kb += 8) {
+    float ac[8], bc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ac[u] = an[u];
+      bc[u] = bn[u];
+    }
+    if (kb + 8 < K / 2) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k2 = 2 * (kb + 8 + u);
+        an[u] = ap[(size_t)k2 * astep];
+        bn[u] = k2 + lk < kvalid ? bp[(size_t)k2 * bstep] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u], bc[u], c, 0, 0, 0);
+  }
+  return c;
+}
+
+// Forward pass of 32 minibatch rows per workgroup (8 waves, one 32-column
+// block each per product), output error e = 2 (y - t) / B, delta2 =
+// [h2 > 0] e w3 and delta1 = [h1 > 0] (delta2 W2); what the gradient needs
+// goes to the scratch arrays.  Odd LDS row strides keep the A reads
+// conflict-free.
+__global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   extern __shared__ __align__(16) float sm[];
   const int run = (int)blockIdx.y;
-  const int tid = (int)threadIdx.x;
-  const int H = a.H, D = a.D;
+  const int tid = (int)threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int li = lane % 32, lk = lane / 32;
+  const int H = a.H, D = a.D, Dp = a.Dp;
   const int b0 = (int)blockIdx.x * kTrainRows;
-  float* xs = sm;                          // [16][D]
-  float* h1 = xs + kTrainRows * D;         // [16][H]
-  float* h2 = h1 + kTrainRows * H;
-  float* d2 = h2 + kTrainRows * H;
-  float* es = d2 + kTrainRows * H;         // [16]
-  int* src = reinterpret_cast<int*>(es + kTrainRows);  // [16]
+  const int sx = Dp + 1, sh = H + 1;
+  float* XS = sm;                       // [32][sx]
+  float* H1 = XS + kTrainRows * sx;     // [32][sh]
+  float* H2 = H1 + kTrainRows * sh;
+  float* D2 = H2 + kTrainRows * sh;
+  float* E = D2 + kTrainRows * sh;      // [32]
+  int* src = reinterpret_cast<int*>(E + kTrainRows);
   const float* th = a.theta + (size_t)run * a.pstride;
   const float* b1 = th + (size_t)H * D;
   const float* W2 = b1 + H;
@@ -495,6 +562,7 @@ __global__ __launch_bounds__(256) void k_train_fwd(SurArgs a) {
   const float b3 = w3[H];
   const float* w1t = a.w1t + (size_t)run * D * H;
   const float* w2t = a.w2t + (size_t)run * H * H;
+  const size_t rb = (size_t)run * a.B + b0;
   if (tid < kTrainRows) {
     const Words4 w = draw_block(kTagTrain, (uint32_t)run, a.step,
                                 (uint32_t)(b0 + tid), 0u, a.mkey_lo,
@@ -502,129 +570,189 @@ __global__ __launch_bounds__(256) void k_train_fwd(SurArgs a) {
     src[tid] = uniform_below(w.w[0], (uint32_t)a.filled);
   }
   __syncthreads();
-  for (int t = tid; t < kTrainRows * D; t += 256) {
-    const int r = t / D, dd = t - r * D;
-    const float v = fmaf(a.ax[((size_t)run * a.cap + src[r]) * a.ldx + dd],
-                         a.xs_mul, a.xs_add);
-    xs[t] = v;
-    a.xsb[((size_t)run * a.B + b0 + r) * a.Dp + dd] = v;
+  for (int t = tid; t < kTrainRows * Dp; t += 512) {
+    const int r = t / Dp, dd = t - r * Dp;
+    const float v =
+        dd < D ? fmaf(a.ax[((size_t)run * a.cap + src[r]) * a.ldx + dd],
+                      a.xs_mul, a.xs_add)
+               : 0.f;
+    XS[r * sx + dd] = v;
+    a.xsb[(rb + r) * Dp + dd] = v;
   }
   __syncthreads();
-  const bool unit = tid < H;
-  float acc[kTrainRows];
-  if (unit) {
+  const int nblk = H / 32;
+  for (int nb = wave; nb < nblk; nb += 8) {  // layer 1: B(k, n) = W1[n][k]
+    const int n = nb * 32 + li;
+    const floatx16 c = mfma_block(XS + li * sx + lk, 1, w1t + (size_t)lk * H + n,
+                                  H, Dp, D, lk);
 #pragma unroll
-    for (int r = 0; r < kTrainRows; ++r) acc[r] = b1[tid];
-    for (int dd = 0; dd < D; ++dd) {
-      const float wv = w1t[(size_t)dd * H + tid];
-#pragma unroll
-      for (int r = 0; r < kTrainRows; ++r) acc[r] = fmaf(wv, xs[r * D + dd], acc[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kTrainRows; ++r) {
-      const float hv = fmaxf(acc[r], 0.f);
-      h1[r * H + tid] = hv;
-      a.h1b[((size_t)run * a.B + b0 + r) * H + tid] = hv;
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(r, lane);
+      const float v = fmaxf(c[r] + b1[n], 0.f);
+      H1[row * sh + n] = v;
+      a.h1b[(rb + row) * H + n] = v;
     }
   }
   __syncthreads();
-  if (unit) {
+  for (int nb = wave; nb < nblk; nb += 8) {  // layer 2: B(k, n) = W2[n][k]
+    const int n = nb * 32 + li;
+    const floatx16 c = mfma_block(H1 + li * sh + lk, 1, w2t + (size_t)lk * H + n,
+                                  H, H, H, lk);
 #pragma unroll
-    for (int r = 0; r < kTrainRows; ++r) acc[r] = b2[tid];
-    for (int j = 0; j < H; ++j) {
-      const float wv = w2t[(size_t)j * H + tid];
-#pragma unroll
-      for (int r = 0; r < kTrainRows; ++r) acc[r] = fmaf(wv, h1[r * H + j], acc[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kTrainRows; ++r) {
-      const float hv = fmaxf(acc[r], 0.f);
-      h2[r * H + tid] = hv;
-      a.h2b[((size_t)run * a.B + b0 + r) * H + tid] = hv;
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(r, lane);
+      const float v = fmaxf(c[r] + b2[n], 0.f);
+      H2[row * sh + n] = v;
+      a.h2b[(rb + row) * H + n] = v;
     }
   }
   __syncthreads();
   {
-    // 16 lanes per row
     const int r = tid / 16, part = tid % 16;
-    float s = 0.f;
-    for (int i = part; i < H; i += 16) s = fmaf(w3[i], h2[r * H + i], s);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    s += __shfl_xor(s, 8, 64);
+    float y = 0.f;
+    for (int i = part; i < H; i += 16) y = fmaf(w3[i], H2[r * sh + i], y);
+    y += __shfl_xor(y, 1, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 4, 64);
+    y += __shfl_xor(y, 8, 64);
     if (part == 0) {
-      const float tgt = a.at[(size_t)run * a.cap + src[r]];
-      const float e = 2.0f * (s + b3 - tgt) / (float)a.B;
-      es[r] = e;
-      a.eb[(size_t)run * a.B + b0 + r] = e;
+      const float e =
+          2.0f * (y + b3 - a.at[(size_t)run * a.cap + src[r]]) / (float)a.B;
+      E[r] = e;
+      a.eb[rb + r] = e;
     }
   }
   __syncthreads();
-  if (unit) {
-#pragma unroll
-    for (int r = 0; r < kTrainRows; ++r) {
-      const float dv = h2[r * H + tid] > 0.f ? es[r] * w3[tid] : 0.f;
-      d2[r * H + tid] = dv;
-      a.d2b[((size_t)run * a.B + b0 + r) * H + tid] = dv;
-    }
+  for (int t = tid; t < kTrainRows * H; t += 512) {
+    const int r = t / H, i = t - r * H;
+    const float dv = H2[r * sh + i] > 0.f ? E[r] * w3[i] : 0.f;
+    D2[r * sh + i] = dv;
+    a.d2b[(rb + r) * H + i] = dv;
   }
   __syncthreads();
-  if (unit) {
+  for (int nb = wave; nb < nblk; nb += 8) {  // delta1: B(k = i, n = j) = W2[i][j]
+    const int n = nb * 32 + li;
+    const floatx16 c = mfma_block(D2 + li * sh + lk, 1, W2 + (size_t)lk * H + n,
+                                  H, H, H, lk);
 #pragma unroll
-    for (int r = 0; r < kTrainRows; ++r) acc[r] = 0.f;
-    for (int i = 0; i < H; ++i) {
-      const float wv = W2[(size_t)i * H + tid];
-#pragma unroll
-      for (int r = 0; r < kTrainRows; ++r) acc[r] = fmaf(wv, d2[r * H + i], acc[r]);
+    for (int r = 0; r < 16; ++r) {
+      const int row = c_row(r, lane);
+      a.d1b[(rb + row) * H + n] = H1[row * sh + n] > 0.f ? c[r] : 0.f;
     }
-#pragma unroll
-    for (int r = 0; r < kTrainRows; ++r)
-      a.d1b[((size_t)run * a.B + b0 + r) * H + tid] =
-          h1[r * H + tid] > 0.f ? acc[r] : 0.f;
   }
 }
 
-// One thread per parameter: gradient summed over the minibatch rows in
-// order, then the Adam update with bias corrections c1, c2.
-__global__ __launch_bounds__(256) void k_train_adam(SurArgs a, int P) {
-  const int H = a.H, D = a.D, B = a.B;
-  const size_t total = (size_t)a.runs * P;
-  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (size_t)gridDim.x * 256) {
-    const int run = (int)(t / P), p = (int)(t - (size_t)run * P);
-    const float* xs = a.xsb + (size_t)run * B * a.Dp;
-    const float* h1 = a.h1b + (size_t)run * B * H;
-    const float* h2 = a.h2b + (size_t)run * B * H;
-    const float* d1 = a.d1b + (size_t)run * B * H;
-    const float* d2 = a.d2b + (size_t)run * B * H;
-    const float* e = a.eb + (size_t)run * B;
-    float g = 0.f;
-    int q = p;
-    if (q < H * D) {
-      const int j = q / D, dd = q - j * D;
-      for (int b = 0; b < B; ++b)
-        g = fmaf(d1[(size_t)b * H + j], xs[(size_t)b * a.Dp + dd], g);
-    } else if ((q -= H * D) < H) {
-      for (int b = 0; b < B; ++b) g += d1[(size_t)b * H + q];
-    } else if ((q -= H) < H * H) {
-      const int i = q / H, j = q - i * H;
-      for (int b = 0; b < B; ++b)
-        g = fmaf(d2[(size_t)b * H + i], h1[(size_t)b * H + j], g);
-    } else if ((q -= H * H) < H) {
-      for (int b = 0; b < B; ++b) g += d2[(size_t)b * H + q];
-    } else if ((q -= H) < H) {
-      for (int b = 0; b < B; ++b) g = fmaf(e[b], h2[(size_t)b * H + q], g);
-    } else {
-      for (int b = 0; b < B; ++b) g += e[b];
-    }
-    const size_t at = (size_t)run * a.pstride + p;
-    const float mv = fmaf(a.beta1, a.m[at], (1.0f - a.beta1) * g);
-    const float vv = fmaf(a.beta2, a.v[at], (1.0f - a.beta2) * g * g);
-    a.m[at] = mv;
-    a.v[at] = vv;
-    a.theta[at] -= a.lr * (mv / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+__device__ __forceinline__ float adam_update(const SurArgs& a, size_t at,
+                                             float g) {
+  const float mv = fmaf(a.beta1, a.m[at], (1.0f - a.beta1) * g);
+  const float vv = fmaf(a.beta2, a.v[at], (1.0f - a.beta2) * g * g);
+  a.m[at] = mv;
+  a.v[at] = vv;
+  const float t = a.theta[at] - a.lr * (mv / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+  a.theta[at] = t;
+  return t;
+}
+
+// Position of element (n, k) of a weight matrix with K padded columns in
+// the BF16 MFMA B-operand layout: block n / 32, K-step k / 16, lane, slot.
+__device__ __forceinline__ size_t frag_index(int n, int k, int K) {
+  const size_t nb = n / 32, kb = k / 16;
+  const int ln = (n % 32) + 32 * ((k % 16) / 8);
+  return ((nb * (K / 16) + kb) * 64 + ln) * 8 + (k % 8);
+}
+
+// Weight-matrix gradients as products over the minibatch, one wave per
+// 32x32 block (W1: delta1^T xs, W2: delta2^T h1), then Adam on each entry.
+__device__ void grad_vec(const SurArgs& a, int run, int t);
+
+// Workgroups 0 .. ceil(blocks / 4) - 1: one wave per 32x32 weight block;
+// the rest: the vector parameters.  Every updated weight is also written to
+// the BF16 inference copy and the FP32 transposed copy.
+__global__ __launch_bounds__(256) void k_train_grad(SurArgs a) {
+  const int run = (int)blockIdx.y;
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int li = lane % 32, lk = lane / 32;
+  const int H = a.H, D = a.D, Dp = a.Dp, B = a.B;
+  const int nbh = H / 32, nbd = Dp / 32;
+  const int nb1 = nbh * nbd, nb2 = nbh * nbh;
+  const int mat_wgs = (nb1 + nb2 + 3) / 4;
+  if ((int)blockIdx.x >= mat_wgs) {
+    grad_vec(a, run, ((int)blockIdx.x - mat_wgs) * 256 + (int)threadIdx.x);
+    return;
   }
+  const int blk = (int)blockIdx.x * 4 + wave;
+  if (blk >= nb1 + nb2) return;  // whole waves; no barrier in this kernel
+  const bool w1 = blk < nb1;
+  const int q = w1 ? blk : blk - nb1;
+  const int ib = w1 ? q / nbd : q / nbh;
+  const int jb = w1 ? q - ib * nbd : q - ib * nbh;
+  const float* dl = (w1 ? a.d1b : a.d2b) + (size_t)run * B * H;
+  const int ldh = w1 ? Dp : H;
+  const float* hv = w1 ? a.xsb + (size_t)run * B * Dp : a.h1b + (size_t)run * B * H;
+  const int i = ib * 32 + li, j = jb * 32 + li;
+  // A(i, b) = delta[b][i], B(b, j) = input[b][j]; B is a multiple of 32
+  const floatx16 c = mfma_block(dl + (size_t)lk * H + i, H,
+                                hv + (size_t)lk * ldh + j, ldh, B, B, lk);
+  const size_t base = (size_t)run * a.pstride;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int ii = ib * 32 + c_row(r, lane), jj = jb * 32 + li;
+    if (w1) {
+      if (jj < D) {
+        const float t = adam_update(a, base + (size_t)ii * D + jj, c[r]);
+        a.w1t[((size_t)run * D + jj) * H + ii] = t;
+        a.w1f[(size_t)run * H * Dp + frag_index(ii, jj, Dp)] = (__bf16)t;
+      }
+    } else {
+      const float t =
+          adam_update(a, base + (size_t)H * D + H + (size_t)ii * H + jj, c[r]);
+      a.w2t[((size_t)run * H + jj) * H + ii] = t;
+      a.w2f[(size_t)run * H * H + frag_index(ii, jj, H)] = (__bf16)t;
+    }
+  }
+}
+
+// Bias and output-layer gradients (3H + 1 per run, t indexes them), summed
+// over the minibatch rows, then Adam.
+__device__ void grad_vec(const SurArgs& a, int run, int t) {
+  const int H = a.H, D = a.D, B = a.B;
+  if (t > 3 * H) return;
+  const float* d1 = a.d1b + (size_t)run * B * H;
+  const float* d2 = a.d2b + (size_t)run * B * H;
+  const float* h2 = a.h2b + (size_t)run * B * H;
+  const float* e = a.eb + (size_t)run * B;
+  // eight partial sums over rows b = u mod 8 (independent load chains),
+  // added in order at the end
+  float gp[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  size_t p;
+  if (t < H) {  // b1
+    for (int b = 0; b < B; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) gp[u] += d1[(size_t)(b + u) * H + t];
+    p = (size_t)H * D + t;
+  } else if (t < 2 * H) {  // b2
+    const int i = t - H;
+    for (int b = 0; b < B; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) gp[u] += d2[(size_t)(b + u) * H + i];
+    p = (size_t)H * D + H + (size_t)H * H + i;
+  } else if (t < 3 * H) {  // w3
+    const int i = t - 2 * H;
+    for (int b = 0; b < B; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        gp[u] = fmaf(e[b + u], h2[(size_t)(b + u) * H + i], gp[u]);
+    p = (size_t)H * D + H + (size_t)H * H + H + i;
+  } else {  // b3
+    for (int b = 0; b < B; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) gp[u] += e[b + u];
+    p = (size_t)H * D + H + (size_t)H * H + 2 * H;
+  }
+  float g = 0.f;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) g += gp[u];
+  adam_update(a, (size_t)run * a.pstride + p, g);
 }
 
 __global__ __launch_bounds__(256) void k_sur_reset(SurArgs a) {
@@ -708,7 +836,7 @@ de_status check(const de_params* p, const de_composition* c,
     if (!std::isfinite(c->bias[k])) return DE_E_INVAL;
   if (s->k < 1 || s->k > 16) return DE_E_INVAL;
   if (s->hidden < 32 || s->hidden > 256 || s->hidden % 32) return DE_E_INVAL;
-  if (s->batch < 16 || s->batch > 1024 || s->batch % 16) return DE_E_INVAL;
+  if (s->batch < 32 || s->batch > 1024 || s->batch % 32) return DE_E_INVAL;
   if (s->archive < s->batch || s->archive < p->NP) return DE_E_INVAL;
   if ((int64_t)s->archive * p->runs > std::numeric_limits<int32_t>::max())
     return DE_E_INVAL;
@@ -721,7 +849,8 @@ de_status check(const de_params* p, const de_composition* c,
   if (de::comp_lds_floats(p->D) * 4 > (size_t)de::kMaxLdsBytes ||
       de::infer_lds_bytes((int)rup(p->D, 32), s->hidden) >
           (size_t)de::kMaxLdsBytes ||
-      de::train_lds_floats(p->D, s->hidden) * 4 > (size_t)de::kMaxLdsBytes)
+      de::train_lds_floats((int)rup(p->D, 32), s->hidden) * 4 >
+          (size_t)de::kMaxLdsBytes)
     return DE_E_UNSUPPORTED;
   return DE_OK;
 }
@@ -905,23 +1034,21 @@ de_status prep_model(de_sur* s, hipStream_t st) {
 }
 
 de_status train_steps(de_sur* s, int n, hipStream_t st) {
-  const int P = (int)model_size(s->p.D, s->sp.hidden);
   for (int k = 0; k < n; ++k) {
     s->step += 1;
     SurArgs a = args_of(s);
     a.c1 = (float)(1.0 - std::pow((double)s->sp.beta1, (double)s->step));
     a.c2 = (float)(1.0 - std::pow((double)s->sp.beta2, (double)s->step));
-    const size_t lds = de::train_lds_floats(a.D, a.H) * 4;
+    const size_t lds = de::train_lds_floats(a.Dp, a.H) * 4;
     hipLaunchKernelGGL(de::k_train_fwd, dim3(a.B / de::kTrainRows, a.runs),
-                       dim3(256), lds, st, a);
+                       dim3(512), lds, st, a);
     de_status rc = from_hip(hipGetLastError());
     if (rc != DE_OK) return rc;
-    hipLaunchKernelGGL(de::k_train_adam,
-                       dim3(grid_for((size_t)a.runs * P, 256)), dim3(256), 0,
-                       st, a, P);
+    const int nblocks = (a.H / 32) * (a.Dp / 32) + (a.H / 32) * (a.H / 32);
+    const int wgs = (nblocks + 3) / 4 + (3 * a.H + 1 + 255) / 256;
+    hipLaunchKernelGGL(de::k_train_grad, dim3(wgs, a.runs), dim3(256), 0, st,
+                       a);
     rc = from_hip(hipGetLastError());
-    if (rc != DE_OK) return rc;
-    rc = prep_model(s, st);
     if (rc != DE_OK) return rc;
   }
   return DE_OK;
