@@ -137,6 +137,7 @@ de_status check_rows(const void* x, int32_t n_rows_hint, int32_t ldx, int D) {
 }
 
 de_status from_hip(hipError_t e) { return e == hipSuccess ? DE_OK : DE_E_DEVICE; }
+#define FROM_HIP(expr) from_hip(DE_NOTE(expr))
 
 GenArgs base_args(const de_state* s) {
   GenArgs a{};
@@ -177,15 +178,15 @@ de_status eval_current_and_reset(de_state* s, hipStream_t st) {
   const int b = (int)(s->gen & 1);
   a.pop_cur = s->pop[b];
   a.fit_next = s->fit[b];
-  de_status rc = from_hip(de::launch_eval(a, s->kind, s->prec, st));
+  de_status rc = FROM_HIP(de::launch_eval(a, s->kind, s->prec, st));
   if (rc != DE_OK) return rc;
-  rc = from_hip(de::launch_stats_reset(a, true, st));
+  rc = FROM_HIP(de::launch_stats_reset(a, true, st));
   if (rc != DE_OK) return rc;
   // the other buffer's rows are unknown: the next step rewrites every row
-  rc = from_hip(de::launch_mark_changed(a, st));
+  rc = FROM_HIP(de::launch_mark_changed(a, st));
   if (rc != DE_OK) return rc;
   a.fit_cur = s->fit[b];
-  return from_hip(de::launch_best_from_fit(a, st));
+  return FROM_HIP(de::launch_best_from_fit(a, st));
 }
 
 // Largest float <= t (so that f <= t in float equals f <= t exactly).
@@ -224,7 +225,7 @@ de_status run_generations(de_state* s, int64_t n, hipStream_t st) {
     a.pop_next = s->pop[b ^ 1];
     a.fit_next = s->fit[b ^ 1];
     const de_status rc =
-        from_hip(de::launch_generation(a, s->kind, s->prec, st));
+        FROM_HIP(de::launch_generation(a, s->kind, s->prec, st));
     if (rc != DE_OK) return rc;
     s->gen += 1;
   }
@@ -342,21 +343,21 @@ de_status init_common(const de_params* params, const de_objective* objective,
     s->jtau_CR = (uint32_t)std::floor((double)jde->tau_CR * 16777216.0);
   }
 
-  rc = from_hip(de::launch_prep(objective->o, objective->R, objective->ldr,
+  rc = FROM_HIP(de::launch_prep(objective->o, objective->R, objective->ldr,
                                 p.D, s->dpad, s->kind, s->prec,
                                 reinterpret_cast<float*>(s->work + L.opad),
                                 L.rop ? s->work + L.rop : nullptr, st));
   if (rc == DE_OK && L.rf32)
-    rc = from_hip(de::launch_copy_rot(objective->R, objective->ldr, p.D,
+    rc = FROM_HIP(de::launch_copy_rot(objective->R, objective->ldr, p.D,
                                       reinterpret_cast<float*>(s->work + L.rf32),
                                       st));
   if (rc == DE_OK) {
     GenArgs a = base_args(s);
     a.pop_next = s->pop[0];
-    rc = from_hip(de::launch_init(a, st));
+    rc = FROM_HIP(de::launch_init(a, st));
   }
   if (rc == DE_OK && jde)
-    rc = from_hip(de::launch_fill_control(
+    rc = FROM_HIP(de::launch_fill_control(
         reinterpret_cast<float2*>(s->work + L.jp[0]), p.runs * p.NP, p.F,
         p.CR, st));
   if (rc == DE_OK) rc = eval_current_and_reset(s, st);
@@ -394,13 +395,13 @@ de_status control_io(de_state* state, void* hip_stream, float* F, float* CR,
   de_status rc = DE_OK;
   if (write) {
     for (size_t k = 0; k < n; ++k) h[k] = make_float2(F[k], CR[k]);
-    rc = from_hip(hipMemcpyAsync(dev, h.data(), 8 * n, hipMemcpyHostToDevice,
+    rc = FROM_HIP(hipMemcpyAsync(dev, h.data(), 8 * n, hipMemcpyHostToDevice,
                                  st));
-    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   } else {
-    rc = from_hip(hipMemcpyAsync(h.data(), dev, 8 * n, hipMemcpyDeviceToHost,
+    rc = FROM_HIP(hipMemcpyAsync(h.data(), dev, 8 * n, hipMemcpyDeviceToHost,
                                  st));
-    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
     if (rc == DE_OK)
       for (size_t k = 0; k < n; ++k) {
         F[k] = h[k].x;
@@ -470,21 +471,21 @@ DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
   // or below it hit at the current generation
   {
     GenArgs r = a;
-    rc = from_hip(de::launch_stats_reset(r, false, st));
+    rc = FROM_HIP(de::launch_stats_reset(r, false, st));
     // launch_stats_reset also clears best; rebuild it from the current fit
     if (rc == DE_OK) {
       r.fit_cur = state->fit[state->gen & 1];
-      rc = from_hip(de::launch_best_from_fit(r, st));
+      rc = FROM_HIP(de::launch_best_from_fit(r, st));
     }
-    if (rc == DE_OK) rc = from_hip(de::launch_hit_check(r, key_of(t32), st));
+    if (rc == DE_OK) rc = FROM_HIP(de::launch_hit_check(r, key_of(t32), st));
   }
   state->target = t32;
   int64_t done_gens = 0;
   while (rc == DE_OK) {
     unsigned int done = 0;
-    rc = from_hip(hipMemcpyAsync(&done, a.done, sizeof(done),
+    rc = FROM_HIP(hipMemcpyAsync(&done, a.done, sizeof(done),
                                  hipMemcpyDeviceToHost, st));
-    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
     if (rc != DE_OK) break;
     if ((int)done >= state->p.runs || done_gens >= max_gens) break;
     const int64_t n = std::min<int64_t>(check_every, max_gens - done_gens);
@@ -497,9 +498,9 @@ DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
     const int runs = state->p.runs;
     unsigned long long* tmp = new (std::nothrow) unsigned long long[runs];
     if (!tmp) return DE_E_NOMEM;
-    rc = from_hip(hipMemcpyAsync(tmp, a.hit_gen, 8 * (size_t)runs,
+    rc = FROM_HIP(hipMemcpyAsync(tmp, a.hit_gen, 8 * (size_t)runs,
                                  hipMemcpyDeviceToHost, st));
-    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
     if (rc == DE_OK)
       for (int r = 0; r < runs; ++r)
         hit_gen[r] = tmp[r] == ~0ull ? -1 : (int64_t)tmp[r];
@@ -515,9 +516,9 @@ DE_API de_status de_best(de_state* state, int32_t run, void* hip_stream,
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const GenArgs a = base_args(state);
   unsigned long long key = 0;
-  de_status rc = from_hip(hipMemcpyAsync(&key, a.best_key + run, 8,
+  de_status rc = FROM_HIP(hipMemcpyAsync(&key, a.best_key + run, 8,
                                          hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc != DE_OK) return rc;
   if (key == ~0ull) return DE_E_STATE;
   const int32_t idx = (int32_t)(key & 0xFFFFFFFFu);
@@ -527,9 +528,9 @@ DE_API de_status de_best(de_state* state, int32_t run, void* hip_stream,
   if (x_host) {
     const float* row = state->pop[state->gen & 1] +
                        ((size_t)run * state->p.NP + idx) * state->ldx;
-    rc = from_hip(hipMemcpyAsync(x_host, row, sizeof(float) * state->p.D,
+    rc = FROM_HIP(hipMemcpyAsync(x_host, row, sizeof(float) * state->p.D,
                                  hipMemcpyDeviceToHost, st));
-    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   }
   return rc;
 }
@@ -550,16 +551,16 @@ DE_API de_status de_best_f64(de_state* state, void* hip_stream,
                           ? reinterpret_cast<const float*>(state->work +
                                                            state->L.rf32)
                           : nullptr;
-  de_status rc = from_hip(de::launch_best_f64(a, state->kind, rf32, f64, idx,
+  de_status rc = FROM_HIP(de::launch_best_f64(a, state->kind, rf32, f64, idx,
                                               st));
   const int runs = state->p.runs;
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(f_host, f64, 8 * (size_t)runs,
+    rc = FROM_HIP(hipMemcpyAsync(f_host, f64, 8 * (size_t)runs,
                                  hipMemcpyDeviceToHost, st));
   if (rc == DE_OK && idx_host)
-    rc = from_hip(hipMemcpyAsync(idx_host, idx, 4 * (size_t)runs,
+    rc = FROM_HIP(hipMemcpyAsync(idx_host, idx, 4 * (size_t)runs,
                                  hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   return rc;
 }
 
@@ -578,12 +579,12 @@ DE_API de_status de_read_stats(de_state* state, void* hip_stream,
   const int runs = state->p.runs;
   unsigned long long* tmp = new (std::nothrow) unsigned long long[2 * runs];
   if (!tmp) return DE_E_NOMEM;
-  de_status rc = from_hip(hipMemcpyAsync(tmp, a.accepted, 8 * (size_t)runs,
+  de_status rc = FROM_HIP(hipMemcpyAsync(tmp, a.accepted, 8 * (size_t)runs,
                                          hipMemcpyDeviceToHost, st));
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(tmp + runs, a.best_key, 8 * (size_t)runs,
+    rc = FROM_HIP(hipMemcpyAsync(tmp + runs, a.best_key, 8 * (size_t)runs,
                                  hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc == DE_OK) {
     for (int r = 0; r < runs; ++r) {
       if (accepted) accepted[r] = (int64_t)tmp[r];
@@ -603,7 +604,7 @@ DE_API de_status de_load_population(de_state* state, int64_t gen,
   state->last_stream = st;
   if (state->jde && ((gen ^ state->gen) & 1)) {
     // jDE: the control values move with the generation's parity
-    const de_status rc = from_hip(hipMemcpyAsync(
+    const de_status rc = FROM_HIP(hipMemcpyAsync(
         state->work + state->L.jp[gen & 1],
         state->work + state->L.jp[state->gen & 1],
         8 * (size_t)state->p.runs * state->p.NP, hipMemcpyDeviceToDevice, st));
@@ -627,7 +628,7 @@ DE_API de_status de_eval(de_state* state, const float* x_dev, int32_t n,
   a.fit_next = f_dev;
   a.nrows = n;
   a.ldx = ldx;
-  return from_hip(de::launch_eval(a, state->kind, state->prec, st));
+  return FROM_HIP(de::launch_eval(a, state->kind, state->prec, st));
 }
 
 DE_API de_status de_debug_draws(const de_state* state, int64_t gen,
@@ -639,7 +640,7 @@ DE_API de_status de_debug_draws(const de_state* state, int64_t gen,
   (void)hipGetLastError();
   GenArgs a = base_args(state);
   a.gen = (uint32_t)gen;
-  return from_hip(de::launch_debug_draws(
+  return FROM_HIP(de::launch_debug_draws(
       a, idx4_dev, mask_dev, reinterpret_cast<hipStream_t>(hip_stream)));
 }
 

@@ -587,6 +587,7 @@ de_status plan_sizes(const de_batch_params* p, Sizes* out) {
 de_status from_hip(hipError_t e) {
   return e == hipSuccess ? DE_OK : DE_E_DEVICE;
 }
+#define FROM_HIP(expr) from_hip(DE_NOTE(expr))
 
 }  // namespace
 
@@ -718,7 +719,7 @@ de_status build_launches(de_batch* b, hipStream_t st,
     const std::vector<BTile>& t = lists.back();
     if (t.empty()) continue;
     BTile* at = dev_tiles + (size_t)v * b->S.L.max_tiles;
-    de_status rc = from_hip(hipMemcpyAsync(at, t.data(), t.size() * sizeof(BTile),
+    de_status rc = FROM_HIP(hipMemcpyAsync(at, t.data(), t.size() * sizeof(BTile),
                                            hipMemcpyHostToDevice, st));
     if (rc != DE_OK) return rc;
     de_batch::Launch l;
@@ -729,7 +730,7 @@ de_status build_launches(de_batch* b, hipStream_t st,
     l.tiles = at;
     b->launches.push_back(l);
   }
-  return from_hip(hipStreamSynchronize(st));
+  return FROM_HIP(hipStreamSynchronize(st));
 }
 
 de_status destroy_graph(de_batch* b) {
@@ -742,7 +743,7 @@ de_status destroy_graph(de_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   b->graph_args.clear();
-  return from_hip(e);
+  return FROM_HIP(e);
 }
 
 // graph_gens generations: per variant a chain of kernel nodes (variants are
@@ -750,7 +751,7 @@ de_status destroy_graph(de_batch* b) {
 de_status build_graph(de_batch* b) {
   const int G = b->graph_gens;
   hipGraph_t g = nullptr;
-  if (hipGraphCreate(&g, 0) != hipSuccess) return DE_E_DEVICE;
+  if (DE_NOTE(hipGraphCreate(&g, 0)) != hipSuccess) return DE_E_DEVICE;
   b->graph = g;
   const BatchArgs base = base_args(b);
   long long* gen_dev = reinterpret_cast<long long*>(b->work + b->S.L.gen);
@@ -791,7 +792,7 @@ de_status build_graph(de_batch* b) {
 de_status direct_generation(de_batch* b, hipStream_t st) {
   BatchArgs a = base_args(b);
   for (const de_batch::Launch& l : b->launches) {
-    const de_status rc = from_hip(launch_variant(b, l.v, false, a, l.ntiles,
+    const de_status rc = FROM_HIP(launch_variant(b, l.v, false, a, l.ntiles,
                                                  l.grid, l.lds, l.tiles, st));
     if (rc != DE_OK) return rc;
   }
@@ -807,11 +808,11 @@ de_status reset_and_best(de_batch* b, hipStream_t st) {
       1024, std::max<size_t>(1, (std::max<size_t>(nrows, b->nruns) + 255) / 256));
   hipLaunchKernelGGL(de::k_bt_reset, dim3(grid), dim3(256), 0, st, a,
                      b->nruns, nrows);
-  de_status rc = from_hip(hipGetLastError());
+  de_status rc = FROM_HIP(hipGetLastError());
   if (rc != DE_OK) return rc;
   hipLaunchKernelGGL(de::k_bt_best, dim3(std::min(b->nruns, 65535)),
                      dim3(256), 0, st, a, b->nruns);
-  return from_hip(hipGetLastError());
+  return FROM_HIP(hipGetLastError());
 }
 
 // Times generation 0 of instance k's runs under variant v (microseconds per
@@ -825,13 +826,13 @@ de_status time_variant(de_batch* b, int k, int v, hipStream_t st, float* us) {
   }
   BTile* at = reinterpret_cast<BTile*>(b->work + b->S.L.tiles) +
               (size_t)DE_BATCH_NVARIANTS * b->S.L.max_tiles;
-  de_status rc = from_hip(hipMemcpyAsync(at, t.data(), t.size() * sizeof(BTile),
+  de_status rc = FROM_HIP(hipMemcpyAsync(at, t.data(), t.size() * sizeof(BTile),
                                          hipMemcpyHostToDevice, st));
   if (rc != DE_OK) return rc;
   const size_t lds = variant_lds(v, b->inst_D[k]);
   const int grid = persistent_grid(b, v, lds, (int)t.size());
   const BatchArgs a = base_args(b);
-  rc = from_hip(launch_variant(b, v, false, a, (int)t.size(), grid, lds, at, st));
+  rc = FROM_HIP(launch_variant(b, v, false, a, (int)t.size(), grid, lds, at, st));
   if (rc != DE_OK) return rc;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return DE_E_DEVICE;
@@ -839,13 +840,13 @@ de_status time_variant(de_batch* b, int k, int v, hipStream_t st, float* us) {
     (void)hipEventDestroy(e0);
     return DE_E_DEVICE;
   }
-  rc = from_hip(hipEventRecord(e0, st));
+  rc = FROM_HIP(hipEventRecord(e0, st));
   for (int rep = 0; rep < kTuneRepeats && rc == DE_OK; ++rep)
-    rc = from_hip(launch_variant(b, v, false, a, (int)t.size(), grid, lds, at, st));
-  if (rc == DE_OK) rc = from_hip(hipEventRecord(e1, st));
-  if (rc == DE_OK) rc = from_hip(hipEventSynchronize(e1));
+    rc = FROM_HIP(launch_variant(b, v, false, a, (int)t.size(), grid, lds, at, st));
+  if (rc == DE_OK) rc = FROM_HIP(hipEventRecord(e1, st));
+  if (rc == DE_OK) rc = FROM_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
-  if (rc == DE_OK) rc = from_hip(hipEventElapsedTime(&ms, e0, e1));
+  if (rc == DE_OK) rc = FROM_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *us = ms * 1000.f / kTuneRepeats;
@@ -875,14 +876,14 @@ de_status eval_default(de_batch* b, hipStream_t st) {
       }
     if (ks.empty()) continue;
     const std::vector<BTile> t = tiles_for(b, ks, variant(v).bm, flat);
-    rc = from_hip(hipMemcpyAsync(scratch, t.data(), t.size() * sizeof(BTile),
+    rc = FROM_HIP(hipMemcpyAsync(scratch, t.data(), t.size() * sizeof(BTile),
                                  hipMemcpyHostToDevice, st));
     if (rc == DE_OK)
-      rc = from_hip(launch_variant(b, v, true, a, (int)t.size(),
+      rc = FROM_HIP(launch_variant(b, v, true, a, (int)t.size(),
                                    persistent_grid(b, v, lds, (int)t.size()),
                                    lds, scratch, st));
     // the scratch list is rewritten by the next variant: wait
-    if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   }
   return rc;
 }
@@ -891,7 +892,7 @@ de_status eval_default(de_batch* b, hipStream_t st) {
 de_status eval_with_launches(de_batch* b, hipStream_t st) {
   const BatchArgs a = base_args(b);
   for (const de_batch::Launch& l : b->launches) {
-    const de_status rc = from_hip(launch_variant(b, l.v, true, a, l.ntiles,
+    const de_status rc = FROM_HIP(launch_variant(b, l.v, true, a, l.ntiles,
                                                  l.grid, l.lds, l.tiles, st));
     if (rc != DE_OK) return rc;
   }
@@ -985,21 +986,21 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
   };
   int dev = 0;
   hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipGetDeviceProperties(&prop, dev) != hipSuccess)
+  if (DE_NOTE(hipGetDevice(&dev)) != hipSuccess ||
+      DE_NOTE(hipGetDeviceProperties(&prop, dev)) != hipSuccess)
     return fail(DE_E_DEVICE);
   b->cus = prop.multiProcessorCount;
   static std::once_flag attr_once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(attr_once, [] {
     for (int v = 0; v < DE_BATCH_NVARIANTS && attr_err == hipSuccess; ++v) {
-      attr_err = hipFuncSetAttribute(variant(v).gen_fn,
+      attr_err = DE_NOTE(hipFuncSetAttribute(variant(v).gen_fn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     de::kMaxLdsBytes);
+                                     de::kMaxLdsBytes));
       if (attr_err == hipSuccess)
-        attr_err = hipFuncSetAttribute(
+        attr_err = DE_NOTE(hipFuncSetAttribute(
             variant(v).eval_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-            de::kMaxLdsBytes);
+            de::kMaxLdsBytes));
     }
   });
   if (attr_err != hipSuccess) return fail(DE_E_DEVICE);
@@ -1031,21 +1032,21 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
     x.dpad_g = dpad_generic(D);
     x.dpad_w = dpad_wide(D);
   }
-  rc = from_hip(hipMemcpyAsync(b->work + L.runs, runs.data(),
+  rc = FROM_HIP(hipMemcpyAsync(b->work + L.runs, runs.data(),
                                sizeof(BRun) * runs.size(),
                                hipMemcpyHostToDevice, st));
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(b->work + L.inst, insts.data(),
+    rc = FROM_HIP(hipMemcpyAsync(b->work + L.inst, insts.data(),
                                  sizeof(BInst) * insts.size(),
                                  hipMemcpyHostToDevice, st));
   for (int k = 0; k < p.ninst && rc == DE_OK; ++k) {
     const de_batch_instance& in = p.inst[k];
     float* opad = reinterpret_cast<float*>(b->work + L.opad_at[k]);
-    rc = from_hip(de::launch_prep(in.o, in.R, in.ldr, in.D, dpad_generic(in.D),
+    rc = FROM_HIP(de::launch_prep(in.o, in.R, in.ldr, in.D, dpad_generic(in.D),
                                   de::kObjRotOsc, de::kPrecBF16, opad,
                                   b->work + L.ropg_at[k], st));
     if (rc == DE_OK && L.ropw_at[k] != L.ropg_at[k])
-      rc = from_hip(de::launch_prep(in.o, in.R, in.ldr, in.D, dpad_wide(in.D),
+      rc = FROM_HIP(de::launch_prep(in.o, in.R, in.ldr, in.D, dpad_wide(in.D),
                                     de::kObjRotOsc, de::kPrecBF16, opad,
                                     b->work + L.ropw_at[k], st));
   }
@@ -1057,7 +1058,7 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
     const int gy = std::min(p.nruns, 65535);
     hipLaunchKernelGGL(de::k_bt_init, dim3(16, gy), dim3(256), 0, st, a,
                        p.nruns);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
   }
   if (rc != DE_OK) return fail(rc);
 
@@ -1107,7 +1108,7 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
   // run comes from one summation order), then fresh statistics
   if (rc == DE_OK) rc = eval_with_launches(b, st);
   if (rc == DE_OK) rc = reset_and_best(b, st);
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc != DE_OK) return fail(rc);
   {
     std::lock_guard<std::mutex> lk(g_live_mu);
@@ -1146,8 +1147,8 @@ DE_API de_status de_batch_generation(de_batch* batch, int64_t n_gens,
     }
     hipLaunchKernelGGL(de::k_bt_set_gen, dim3(1), dim3(1), 0, st, gen_dev,
                        (long long)batch->gen);
-    rc = from_hip(hipGetLastError());
-    if (rc == DE_OK) rc = from_hip(hipGraphLaunch(batch->exec, st));
+    rc = FROM_HIP(hipGetLastError());
+    if (rc == DE_OK) rc = FROM_HIP(hipGraphLaunch(batch->exec, st));
     if (rc == DE_OK) {
       batch->gen += G;
       n_gens -= G;
@@ -1167,15 +1168,15 @@ DE_API de_status de_batch_read(de_batch* batch, void* hip_stream,
   const size_t n = (size_t)batch->nruns;
   std::vector<unsigned long long> key(n), acc(n), hit(n);
   const BLayout& L = batch->S.L;
-  de_status rc = from_hip(hipMemcpyAsync(key.data(), batch->work + L.best,
+  de_status rc = FROM_HIP(hipMemcpyAsync(key.data(), batch->work + L.best,
                                          8 * n, hipMemcpyDeviceToHost, st));
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(acc.data(), batch->work + L.acc, 8 * n,
+    rc = FROM_HIP(hipMemcpyAsync(acc.data(), batch->work + L.acc, 8 * n,
                                  hipMemcpyDeviceToHost, st));
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(hit.data(), batch->work + L.hit, 8 * n,
+    rc = FROM_HIP(hipMemcpyAsync(hit.data(), batch->work + L.hit, 8 * n,
                                  hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc != DE_OK) return rc;
   for (size_t r = 0; r < n; ++r) {
     const uint32_t ord = (uint32_t)(key[r] >> 32);

@@ -38,6 +38,11 @@ struct GenArgs {
   uint32_t jtau_F, jtau_CR;
 };
 
+// A HIP call's status, reported on stderr with its source location when the
+// environment variable DE_DEBUG is set and the call failed.
+hipError_t note_hip(hipError_t e, const char* file, int line);
+#define DE_NOTE(expr) ::de::note_hip((expr), __FILE__, __LINE__)
+
 size_t rot_lds_bytes_host(int prec, int dpad, bool jde = false);
 bool sep_supported(int D);
 

@@ -18,6 +18,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "de_device.hpp"
 #include "de_internal.h"
 #include "de_tile.hpp"
@@ -439,6 +442,16 @@ size_t rot_lds_bytes_host(int prec, int dpad, bool jde) {
 }
 
 bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
+
+hipError_t note_hip(hipError_t e, const char* file, int line) {
+  if (e != hipSuccess) {
+    static const bool on = std::getenv("DE_DEBUG") != nullptr;
+    if (on)
+      std::fprintf(stderr, "libde: %s:%d: %s (%s)\n", file, line,
+                   hipGetErrorName(e), hipGetErrorString(e));
+  }
+  return e;
+}
 
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,
                              hipStream_t s) {

@@ -898,6 +898,7 @@ SLayout layout(const de_params& p, const de_composition& c,
 de_status from_hip(hipError_t e) {
   return e == hipSuccess ? DE_OK : DE_E_DEVICE;
 }
+#define FROM_HIP(expr) from_hip(DE_NOTE(expr))
 
 int grid_for(size_t work, int per) {
   size_t b = (work + per - 1) / per;
@@ -1021,7 +1022,7 @@ de_status set_lds_attributes() {
             de::kMaxLdsBytes - (int)fa.sharedSizeBytes);
     }
   });
-  return from_hip(err);
+  return FROM_HIP(err);
 }
 
 de_status prep_model(de_sur* s, hipStream_t st) {
@@ -1030,7 +1031,7 @@ de_status prep_model(de_sur* s, hipStream_t st) {
                       ((size_t)a.H * a.Dp + (size_t)a.H * a.H);
   hipLaunchKernelGGL(de::k_model_prep, dim3(grid_for(work, 256)), dim3(256), 0,
                      st, a);
-  return from_hip(hipGetLastError());
+  return FROM_HIP(hipGetLastError());
 }
 
 de_status train_steps(de_sur* s, int n, hipStream_t st) {
@@ -1042,13 +1043,13 @@ de_status train_steps(de_sur* s, int n, hipStream_t st) {
     const size_t lds = de::train_lds_floats(a.Dp, a.H) * 4;
     hipLaunchKernelGGL(de::k_train_fwd, dim3(a.B / de::kTrainRows, a.runs),
                        dim3(512), lds, st, a);
-    de_status rc = from_hip(hipGetLastError());
+    de_status rc = FROM_HIP(hipGetLastError());
     if (rc != DE_OK) return rc;
     const int nblocks = (a.H / 32) * (a.Dp / 32) + (a.H / 32) * (a.H / 32);
     const int wgs = (nblocks + 3) / 4 + (3 * a.H + 1 + 255) / 256;
     hipLaunchKernelGGL(de::k_train_grad, dim3(wgs, a.runs), dim3(256), 0, st,
                        a);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
     if (rc != DE_OK) return rc;
   }
   return DE_OK;
@@ -1062,7 +1063,7 @@ de_status comp_eval(const de_sur* s, const float* X, int n, int ldx, float* f,
   hipLaunchKernelGGL(de::k_comp_eval,
                      dim3((n + de::kEvalRows - 1) / de::kEvalRows),
                      dim3(de::kEvalThreads), lds, st, a, X, n, ldx, f);
-  return from_hip(hipGetLastError());
+  return FROM_HIP(hipGetLastError());
 }
 
 de_status one_generation(de_sur* s, hipStream_t st) {
@@ -1071,7 +1072,7 @@ de_status one_generation(de_sur* s, hipStream_t st) {
   s->last_use_model = a.use_model;
   hipLaunchKernelGGL(de::k_sur_cand, dim3((a.NP * a.k + 3) / 4, a.runs),
                      dim3(256), 0, st, a);
-  de_status rc = from_hip(hipGetLastError());
+  de_status rc = FROM_HIP(hipGetLastError());
   if (rc != DE_OK) return rc;
   if (a.use_model) {
     const int rows = a.NP * a.k;
@@ -1081,10 +1082,10 @@ de_status one_generation(de_sur* s, hipStream_t st) {
                        dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a,
                        (const float*)a.cand, (size_t)rows * a.ldx, rows, a.ldx,
                        a.pred, (size_t)rows, 0);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
     if (rc != DE_OK) return rc;
   } else {
-    rc = from_hip(hipMemsetAsync(a.pred, 0,
+    rc = FROM_HIP(hipMemsetAsync(a.pred, 0,
                                  4 * (size_t)a.runs * a.NP * a.k, st));
     if (rc != DE_OK) return rc;
   }
@@ -1092,7 +1093,7 @@ de_status one_generation(de_sur* s, hipStream_t st) {
                      dim3((a.NP + de::kEvalRows - 1) / de::kEvalRows, a.runs),
                      dim3(de::kEvalThreads), de::comp_lds_floats(a.D) * 4, st,
                      a);
-  rc = from_hip(hipGetLastError());
+  rc = FROM_HIP(hipGetLastError());
   if (rc != DE_OK) return rc;
   s->gen += 1;
   s->rounds += 1;
@@ -1171,9 +1172,9 @@ DE_API de_status de_sur_init(const de_params* params,
                      dim3(grid_for((size_t)comp->n * p.D * p.D, 256)),
                      dim3(256), 0, st, comp->O, comp->R, comp->ldr, comp->n,
                      p.D, const_cast<float*>(a.O), const_cast<float*>(a.Rt));
-  rc = from_hip(hipGetLastError());
+  rc = FROM_HIP(hipGetLastError());
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(const_cast<float*>(a.bias), comp->bias,
+    rc = FROM_HIP(hipMemcpyAsync(const_cast<float*>(a.bias), comp->bias,
                                  4 * (size_t)comp->n, hipMemcpyHostToDevice,
                                  st));
   // generation 0 (the per-problem initialisation kernel, same draws)
@@ -1189,7 +1190,7 @@ DE_API de_status de_sur_init(const de_params* params,
     g.hi = p.hi;
     g.key_lo = (uint32_t)p.seed;
     g.key_hi = (uint32_t)(p.seed >> 32);
-    rc = from_hip(de::launch_init(g, st));
+    rc = FROM_HIP(de::launch_init(g, st));
   }
   if (rc == DE_OK)
     rc = comp_eval(s, s->pop[0], p.runs * p.NP, s->ldx, s->fit[0], st);
@@ -1198,26 +1199,26 @@ DE_API de_status de_sur_init(const de_params* params,
                        dim3(grid_for((size_t)p.runs * p.NP * ((p.D + 3) / 4),
                                      256)),
                        dim3(256), 0, st, a);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
   }
   if (rc == DE_OK) {
     hipLaunchKernelGGL(de::k_sur_reset, dim3(grid_for(p.runs, 256)),
                        dim3(256), 0, st, a);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
   }
   if (rc == DE_OK) {
     hipLaunchKernelGGL(de::k_sur_best, dim3(p.runs), dim3(256), 0, st, a);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
   }
   if (rc == DE_OK) {
     const int P = (int)model_size(p.D, sp->hidden);
     hipLaunchKernelGGL(de::k_model_init,
                        dim3(grid_for((size_t)p.runs * L.pstride, 256)),
                        dim3(256), 0, st, a, P);
-    rc = from_hip(hipGetLastError());
+    rc = FROM_HIP(hipGetLastError());
   }
   if (rc == DE_OK) rc = prep_model(s, st);
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc != DE_OK) return fail(rc);
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1248,12 +1249,12 @@ DE_API de_status de_sur_read(de_sur* s, void* hip_stream, double* best_f,
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const size_t n = (size_t)s->p.runs;
   std::vector<unsigned long long> key(n), acc(n);
-  de_status rc = from_hip(hipMemcpyAsync(key.data(), s->work + s->L.best,
+  de_status rc = FROM_HIP(hipMemcpyAsync(key.data(), s->work + s->L.best,
                                          8 * n, hipMemcpyDeviceToHost, st));
   if (rc == DE_OK)
-    rc = from_hip(hipMemcpyAsync(acc.data(), s->work + s->L.acc, 8 * n,
+    rc = FROM_HIP(hipMemcpyAsync(acc.data(), s->work + s->L.acc, 8 * n,
                                  hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc != DE_OK) return rc;
   for (size_t r = 0; r < n; ++r) {
     const uint32_t ord = (uint32_t)(key[r] >> 32);
@@ -1299,7 +1300,7 @@ DE_API de_status de_sur_predict(de_sur* s, int32_t run, const float* x_dev,
                      dim3((n + de::kInferRows - 1) / de::kInferRows, 1),
                      dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a, x_dev,
                      (size_t)0, n, ldx, y_dev, (size_t)0, run);
-  return from_hip(hipGetLastError());
+  return FROM_HIP(hipGetLastError());
 }
 
 DE_API de_status de_sur_get_model(de_sur* s, void* hip_stream, float* theta,
@@ -1314,12 +1315,12 @@ DE_API de_status de_sur_get_model(de_sur* s, void* hip_stream, float* theta,
   for (int q = 0; q < 3 && rc == DE_OK; ++q) {
     if (!dst[q]) continue;
     for (int r = 0; r < s->p.runs && rc == DE_OK; ++r)
-      rc = from_hip(hipMemcpyAsync(
+      rc = FROM_HIP(hipMemcpyAsync(
           dst[q] + (size_t)r * P,
           s->work + src[q] + 4 * (size_t)r * s->L.pstride, 4 * P,
           hipMemcpyDeviceToHost, st));
   }
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc == DE_OK && step) *step = s->step;
   return rc;
 }
@@ -1343,11 +1344,11 @@ DE_API de_status de_sur_set_model(de_sur* s, void* hip_stream,
   de_status rc = DE_OK;
   for (int q = 0; q < 3 && rc == DE_OK; ++q)
     for (int r = 0; r < s->p.runs && rc == DE_OK; ++r)
-      rc = from_hip(hipMemcpyAsync(
+      rc = FROM_HIP(hipMemcpyAsync(
           s->work + dst[q] + 4 * (size_t)r * s->L.pstride,
           srcs[q] + (size_t)r * P, 4 * P, hipMemcpyHostToDevice, st));
   if (rc == DE_OK) rc = prep_model(s, st);
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc == DE_OK) s->step = step;
   return rc;
 }
@@ -1367,13 +1368,13 @@ DE_API de_status de_sur_get_archive(de_sur* s, void* hip_stream, float* X,
   const size_t cap = (size_t)s->sp.archive, R = (size_t)s->p.runs;
   de_status rc = DE_OK;
   if (X)
-    rc = from_hip(hipMemcpy2DAsync(X, 4 * (size_t)s->p.D, s->work + s->L.ax,
+    rc = FROM_HIP(hipMemcpy2DAsync(X, 4 * (size_t)s->p.D, s->work + s->L.ax,
                                    4 * (size_t)s->ldx, 4 * (size_t)s->p.D,
                                    R * cap, hipMemcpyDeviceToHost, st));
   if (rc == DE_OK && T)
-    rc = from_hip(hipMemcpyAsync(T, s->work + s->L.at, 4 * R * cap,
+    rc = FROM_HIP(hipMemcpyAsync(T, s->work + s->L.at, 4 * R * cap,
                                  hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   if (rc == DE_OK && filled)
     for (size_t r = 0; r < R; ++r)
       filled[r] = std::min<int64_t>(s->sp.archive, s->rounds * s->p.NP);
@@ -1389,17 +1390,17 @@ DE_API de_status de_sur_last(de_sur* s, void* hip_stream, float* cand,
                k = (size_t)s->sp.k;
   de_status rc = DE_OK;
   if (cand)
-    rc = from_hip(hipMemcpy2DAsync(cand, 4 * (size_t)s->p.D,
+    rc = FROM_HIP(hipMemcpy2DAsync(cand, 4 * (size_t)s->p.D,
                                    s->work + s->L.cand, 4 * (size_t)s->ldx,
                                    4 * (size_t)s->p.D, R * NP * k,
                                    hipMemcpyDeviceToHost, st));
   if (rc == DE_OK && pred)
-    rc = from_hip(hipMemcpyAsync(pred, s->work + s->L.pred, 4 * R * NP * k,
+    rc = FROM_HIP(hipMemcpyAsync(pred, s->work + s->L.pred, 4 * R * NP * k,
                                  hipMemcpyDeviceToHost, st));
   if (rc == DE_OK && choice)
-    rc = from_hip(hipMemcpyAsync(choice, s->work + s->L.choice, 4 * R * NP,
+    rc = FROM_HIP(hipMemcpyAsync(choice, s->work + s->L.choice, 4 * R * NP,
                                  hipMemcpyDeviceToHost, st));
-  if (rc == DE_OK) rc = from_hip(hipStreamSynchronize(st));
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   return rc;
 }
 

@@ -14,6 +14,11 @@ from __future__ import annotations
 import ctypes
 import os
 
+# The library must bind to the HIP runtime PyTorch loads (PyTorch ships its
+# own copy, and streams and device pointers come from it): import PyTorch
+# before the library, or the process can end up with two HIP runtimes.
+import torch  # noqa: F401
+
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libde.so")
 
