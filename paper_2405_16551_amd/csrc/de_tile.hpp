@@ -114,11 +114,9 @@ __device__ __forceinline__ void osc_accumulate(floatx16& part,
   for (int r = 0; r < 16; ++r) part[r] += osc_term<kFastSin>(c[r]);
 }
 
-// Target and donor chunks of one row, for a group of four 256-coordinate
-// chunks.
-struct RowChunks {
-  float4 xv[4], v1[4], v2[4], v3[4];
-};
+// 256-coordinate chunks per producer step (rows per step: 8 / this).  One
+// chunk of eight rows measured fastest at D = 1000 (BF16 and FP32 tiles).
+constexpr int kProducerChunks = 1;
 
 // R fragments of four consecutive K-steps for two column blocks.
 struct BFrags {
@@ -224,24 +222,29 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     for (int k = lane; k < dpad; k += 64) arow[k] = (T)0.0f;
   }
   {
-    // Rows rl = wave + kRotWaves * k of this wave, two rows per step: the
-    // target and donor chunks of both rows (groups of four 256-coordinate
-    // chunks) are requested together, then drawn, mutated and stored.
-    // Loads past the end of a row go to its last chunk (values unused), so
-    // no load sits behind a per-lane branch.
+    // Chunk-major: for each group of CG 256-coordinate chunks, the wave's
+    // rows rl = wave + kRotWaves * k go RB at a time (CG * RB = 8 chunk
+    // rows in flight): the target and donor chunks of the RB rows are
+    // requested together, then drawn, mutated and stored.  All workgroups
+    // walk the chunks in the same order, so an XCD's donor reads of one
+    // step stay within one chunk of its runs' rows (a working set its L2
+    // holds).  Loads past the end of a row go to its last chunk and rows
+    // past the wave's last go to its last row (values unused), so no load
+    // sits behind a per-lane branch.
+    constexpr int CG = kProducerChunks;
+    constexpr int RB = 8 / CG;
     const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
     const int dlast = ((a.D + 3) / 4 - 1) * 4;
-    for (int t0 = 0; t0 < tq; t0 += 4) {
-      float4 ov[4];
+    for (int t0 = 0; t0 < tq; t0 += CG) {
+      float4 ov[CG];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < CG; ++u)
         ov[u] = ld4(a.o + min(4 * (lane + 64 * (t0 + u)), dlast));
-      for (int k = 0; k < nrow_w; k += 2) {
-        const bool two = k + 1 < nrow_w;
-        RowChunks c[2];
+      for (int k = 0; k < nrow_w; k += RB) {
+        float4 xv[RB][CG], v1[RB][CG], v2[RB][CG], v3[RB][CG];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int rl = wave + kRotWaves * (two ? k + h : k);
+        for (int h = 0; h < RB; ++h) {
+          const int rl = wave + kRotWaves * min(k + h, nrow_w - 1);
           const float* xrow = base + (size_t)(row0 + rl) * a.ldx;
           const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
           if (!EVAL) {
@@ -250,19 +253,19 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
             x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < CG; ++u) {
             const int jl = min(4 * (lane + 64 * (t0 + u)), dlast);
-            c[h].xv[u] = ld4(xrow + jl);
+            xv[h][u] = ld4(xrow + jl);
             if (!EVAL) {
-              c[h].v1[u] = ld4(x1 + jl);
-              c[h].v2[u] = ld4(x2 + jl);
-              c[h].v3[u] = ld4(x3 + jl);
+              v1[h][u] = ld4(x1 + jl);
+              v2[h][u] = ld4(x2 + jl);
+              v3[h][u] = ld4(x3 + jl);
             }
           }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if (h == 1 && !two) break;
+        for (int h = 0; h < RB; ++h) {
+          if (k + h >= nrow_w) break;
           const int rl = wave + kRotWaves * (k + h);
           const int i = row0 + rl;
           const int jrand = EVAL ? 0 : donors[rl * 4 + 3];
@@ -275,12 +278,12 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
           }
           T* arow = At + (size_t)rl * stride;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < CG; ++u) {
             const int t = t0 + u;
             if (t >= tq) break;
             const int q = lane + 64 * t, j0 = 4 * q;
             uint32_t bits = 0;
-            float4 uu = c[h].xv[u];
+            float4 uu = xv[h][u];
             if (!EVAL) {
               const Words4 w = draw_block(kTagXover, rng_run, a.gen,
                                           (uint32_t)i, (uint32_t)q, a.key_lo,
@@ -291,9 +294,9 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
                     (j0 + b < a.D) &&
                     take_mutant(w.w[b], j0 + b, jrand, crt);
                 const float mv =
-                    mutant_coord(get(c[h].v1[u], b), get(c[h].v2[u], b),
-                                 get(c[h].v3[u], b), Fr, a.lo, a.hi);
-                set(uu, b, tk ? mv : get(c[h].xv[u], b));
+                    mutant_coord(get(v1[h][u], b), get(v2[h][u], b),
+                                 get(v3[h][u], b), Fr, a.lo, a.hi);
+                set(uu, b, tk ? mv : get(xv[h][u], b));
                 bits |= (tk ? 1u : 0u) << b;
               }
             }
