@@ -238,7 +238,10 @@ def describe_surrogate(runs=SUR_RUNS):
 def time_surrogate(gens=300, check_every=10, runs=SUR_RUNS):
     """Plain form (k = 1, no model, same kernels) for `gens` generations,
     then the surrogate form until its median best reaches the plain form's
-    final median best (or 2 * gens generations); wall-clock both."""
+    final median best (or 2 * gens generations).  Reported: wall clock of
+    both (host included, median read every `check_every` generations) and
+    the GPU time to the same best from each form's steady-state time per
+    generation (HIP events)."""
     import numpy as np
     import torch
 
@@ -248,9 +251,25 @@ def time_surrogate(gens=300, check_every=10, runs=SUR_RUNS):
     comp = instances.make_composition(100, 8, 1)
     common = dict(runs=runs, NP=512, D=100, F=0.5, CR=0.9, comp=comp, seed=1,
                   hidden=256, batch=256, archive=16384)
+    # clocks up before anything is timed: a throwaway run of both forms
+    for kw in (dict(k=1, steps=0, warmup_gens=0),
+               dict(k=4, steps=1, warmup_gens=0)):
+        w = SurrogateDE(**kw, **dict(common, seed=99))
+        w.generation(60)
+        w.read()
+        w.close()
     plain = SurrogateDE(k=1, steps=0, warmup_gens=0, **common)
     sur = SurrogateDE(k=4, steps=1, warmup_gens=5, **common)
     torch.cuda.synchronize()
+
+    def gen_ms(s, n=30):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.generation(n)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
 
     def run(s, stop):
         t0 = time.perf_counter()
@@ -269,17 +288,22 @@ def time_surrogate(gens=300, check_every=10, runs=SUR_RUNS):
     target = trp[-1][1]
     ts, gs, trs = run(sur, (2 * gens, target))
     reached = trs[-1][1] <= target
+    # steady-state GPU time per generation of each form (events)
+    mp, ms_ = gen_ms(plain), gen_ms(sur)
     plain.close()
     sur.close()
     return dict(
         workload=describe_surrogate(runs), runs=runs,
         plain=dict(generations=gp, seconds=round(tp, 3),
                    ms_per_gen=round(tp / gp * 1e3, 4),
-                   median_best=target),
+                   gpu_ms_per_gen=round(mp, 4), median_best=target),
         surrogate=dict(generations=gs, seconds=round(ts, 3),
                        ms_per_gen=round(ts / gs * 1e3, 4),
+                       gpu_ms_per_gen=round(ms_, 4),
                        median_best=trs[-1][1], reached_plain_best=reached),
         speedup_to_same_best=round(tp / ts, 3) if reached else None,
+        gpu_time_speedup_to_same_best=(round(gp * mp / (gs * ms_), 3)
+                                       if reached else None),
         true_evals_ratio=round(gs / gp, 3))
 
 

@@ -198,12 +198,19 @@ __global__ __launch_bounds__(kEvalThreads) void k_comp_eval(SurArgs a,
 }
 
 // ---------------------------------------------------------------------------
-// Candidates: one wave per candidate row (i, c), lanes over 4-groups.
+// Candidates: one wave per candidate row (i, c), or one half-wave when a
+// row has at most 32 4-groups; lanes over 4-groups.
+__host__ __device__ constexpr int cand_rows_per_wave(int D) {
+  return (D + 3) / 4 <= 32 ? 2 : 1;
+}
+
 __global__ __launch_bounds__(256) void k_sur_cand(SurArgs a) {
   const int run = (int)blockIdx.y;
-  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
-  const int cr = (int)blockIdx.x * 4 + wave;
-  if (cr >= a.NP * a.k) return;  // whole waves leave together
+  const int wave = (int)threadIdx.x / 64;
+  const int rpw = cand_rows_per_wave(a.D), lpr = 64 / rpw;
+  const int lane = (int)threadIdx.x % lpr;
+  const int cr = ((int)blockIdx.x * 4 + wave) * rpw + ((int)threadIdx.x % 64) / lpr;
+  if (cr >= a.NP * a.k) return;  // whole row groups leave together
   const int i = cr / a.k, c = cr - i * a.k;
   const uint32_t ctr_i = (uint32_t)i | ((uint32_t)c << 24);
   const Donors d = pick_donors_ctr((uint32_t)run, a.gen, ctr_i, i, a.NP, a.D,
@@ -214,8 +221,10 @@ __global__ __launch_bounds__(256) void k_sur_cand(SurArgs a) {
   const float* x2 = base + (size_t)d.r2 * a.ldx;
   const float* x3 = base + (size_t)d.r3 * a.ldx;
   float* out = a.cand + ((size_t)run * a.NP * a.k + cr) * a.ldx;
+  // predictions read 0 for a generation the model does not screen
+  if (!a.use_model && lane == 0) a.pred[(size_t)run * a.NP * a.k + cr] = 0.f;
   const int nq = (a.D + 3) / 4;
-  for (int q = lane; q < nq; q += 64) {
+  for (int q = lane; q < nq; q += lpr) {
     const int j0 = 4 * q;
     const float4 xv = ld4(x + j0), v1 = ld4(x1 + j0), v2 = ld4(x2 + j0),
                  v3 = ld4(x3 + j0);
@@ -237,37 +246,81 @@ __global__ __launch_bounds__(256) void k_sur_cand(SurArgs a) {
 // ---------------------------------------------------------------------------
 // MLP inference on MFMA: rows of X (row r at X + r * ldx) of run
 // run0 + blockIdx.y, 32 rows per workgroup of 256 threads.
-constexpr int kInferRows = 32;
+constexpr int kInferRows = 64;
 
 __host__ __device__ constexpr size_t infer_lds_bytes(int Dp, int H) {
   return (size_t)kInferRows * (Dp + 8) * 2 + (size_t)kInferRows * (H + 8) * 2 +
-         (size_t)kInferRows * H * 4;
+         (size_t)4 * kInferRows * 4;
 }
 
-// One 32x32 BF16 block over kbn K-steps of 16 (kbn even): A fragments
-// from LDS at ar + 16 kb, B fragments at wf[kb * 64]; two K-steps per batch,
-// each batch's reads issued one batch ahead.
-__device__ __forceinline__ floatx16 mfma_bf16_block(const __bf16* ar,
-                                                    const bf16x8* wf,
-                                                    int kbn) {
-  floatx16 c = {};
-  bf16x8 an0 = *reinterpret_cast<const bf16x8*>(ar);
-  bf16x8 an1 = *reinterpret_cast<const bf16x8*>(ar + 16);
-  bf16x8 bn0 = wf[0], bn1 = wf[64];
-  for (int kb = 0; kb < kbn; kb += 2) {
-    const bf16x8 a0 = an0, a1 = an1, b0 = bn0, b1 = bn1;
-    if (kb + 2 < kbn) {
-      an0 = *reinterpret_cast<const bf16x8*>(ar + 16 * (kb + 2));
-      an1 = *reinterpret_cast<const bf16x8*>(ar + 16 * (kb + 3));
-      bn0 = wf[(size_t)(kb + 2) * 64];
-      bn1 = wf[(size_t)(kb + 3) * 64];
-    }
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, c, 0, 0, 0);
+// Two 32x32 BF16 blocks (row blocks 0 and 1, same columns) over kbn
+// K-steps of 16 (kbn even): A fragments from LDS at ar0 / ar1 + 16 kb, B
+// fragments at wf[kb * 64], each B fragment used by both row blocks; two
+// K-steps per batch, each batch's reads issued one batch ahead.
+__device__ __forceinline__ void mfma_bf16_pair(const __bf16* ar0,
+                                               const __bf16* ar1,
+                                               const bf16x8* wf, int kbn,
+                                               floatx16& c0, floatx16& c1) {
+  c0 = floatx16{};
+  c1 = floatx16{};
+  bf16x8 a0n[2], a1n[2], bn[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    a0n[u] = *reinterpret_cast<const bf16x8*>(ar0 + 16 * u);
+    a1n[u] = *reinterpret_cast<const bf16x8*>(ar1 + 16 * u);
+    bn[u] = wf[(size_t)u * 64];
   }
-  return c;
+  for (int kb = 0; kb < kbn; kb += 2) {
+    bf16x8 a0[2], a1[2], b[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      a0[u] = a0n[u];
+      a1[u] = a1n[u];
+      b[u] = bn[u];
+    }
+    if (kb + 2 < kbn) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        a0n[u] = *reinterpret_cast<const bf16x8*>(ar0 + 16 * (kb + 2 + u));
+        a1n[u] = *reinterpret_cast<const bf16x8*>(ar1 + 16 * (kb + 2 + u));
+        bn[u] = wf[(size_t)(kb + 2 + u) * 64];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], b[u], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], b[u], c1, 0, 0, 0);
+    }
+  }
 }
 
+// Sum over the 32 lanes of each half-wave of 16 per-lane row values
+// (register r holds row 8 (r / 4) + 4 (l / 32) + r % 4 of a 32-row block):
+// four reduce-scatter steps over lane bits 4..1, then lanes l, l ^ 1; lane
+// l ends with row r = (l % 32) / 2 in the returned value.
+__device__ __forceinline__ float rows_of_block(const floatx16& part,
+                                               int lane) {
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = part[r];
+#pragma unroll
+  for (int m = 16; m >= 2; m >>= 1) {
+    const bool upper = (lane & m) != 0;
+#pragma unroll
+    for (int k = 0; k < m / 2; ++k) {
+      const float send = upper ? v[k] : v[k + m / 2];
+      const float keep = upper ? v[k + m / 2] : v[k];
+      v[k] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+// MLP inference on MFMA: rows of X (row r at X + r * ldx) of run
+// run0 + blockIdx.y, 64 rows per workgroup of 256 threads (4 waves, each
+// two 32-column blocks per layer over both 32-row blocks).  Layer 1 writes
+// relu(A W1^T + b1) to LDS in BF16; layer 2's epilogue applies relu(. + b2)
+// and the output weights w3 directly, so only per-wave row sums remain.
 __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
                                                    size_t x_run_stride, int n,
                                                    int ldx, float* y,
@@ -281,7 +334,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
   const int sa = Dp + 8, sh = H + 8;
   __bf16* A = reinterpret_cast<__bf16*>(smem);
   __bf16* H1 = A + (size_t)kInferRows * sa;
-  float* H2 = reinterpret_cast<float*>(H1 + (size_t)kInferRows * sh);
+  float* ypart = reinterpret_cast<float*>(H1 + (size_t)kInferRows * sh);
   const float* Xr = X + blockIdx.y * x_run_stride;
   const float* th = a.theta + (size_t)run * a.pstride;
   const float* b1 = th + (size_t)H * a.D;
@@ -297,51 +350,60 @@ __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
   }
   __syncthreads();
   const int nblk = H / 32;
-  // layer 1: H1 = relu(A W1^T + b1), BF16
+  const int li = lane % 32, lk = lane / 32;
   {
     const int kbn = Dp / 16;
     const bf16x8* wf = reinterpret_cast<const bf16x8*>(a.w1f) +
-                       (size_t)run * nblk * kbn * 64;
-    const __bf16* ar = A + (size_t)(lane % 32) * sa + 8 * (lane / 32);
+                       (size_t)run * nblk * kbn * 64 + lane;
+    const __bf16* ar0 = A + (size_t)li * sa + 8 * lk;
+    const __bf16* ar1 = ar0 + (size_t)32 * sa;
     for (int nb = wave; nb < nblk; nb += 4) {
-      const floatx16 c =
-          mfma_bf16_block(ar, wf + (size_t)nb * kbn * 64 + lane, kbn);
-      const int col = nb * 32 + lane % 32;
+      floatx16 c0, c1;
+      mfma_bf16_pair(ar0, ar1, wf + (size_t)nb * kbn * 64, kbn, c0, c1);
+      const int col = nb * 32 + li;
+      const float bb = b1[col];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        H1[row * sh + col] = (__bf16)fmaxf(c[r] + b1[col], 0.f);
+        const int row = 8 * (r / 4) + 4 * lk + (r % 4);
+        H1[row * sh + col] = (__bf16)fmaxf(c0[r] + bb, 0.f);
+        H1[(32 + row) * sh + col] = (__bf16)fmaxf(c1[r] + bb, 0.f);
       }
     }
   }
   __syncthreads();
-  // layer 2: H2 = relu(H1 W2^T + b2), FP32
   {
     const int kbn = H / 16;
     const bf16x8* wf = reinterpret_cast<const bf16x8*>(a.w2f) +
-                       (size_t)run * nblk * kbn * 64;
-    const __bf16* ar = H1 + (size_t)(lane % 32) * sh + 8 * (lane / 32);
+                       (size_t)run * nblk * kbn * 64 + lane;
+    const __bf16* ar0 = H1 + (size_t)li * sh + 8 * lk;
+    const __bf16* ar1 = ar0 + (size_t)32 * sh;
+    floatx16 p0 = {}, p1 = {};
     for (int nb = wave; nb < nblk; nb += 4) {
-      const floatx16 c =
-          mfma_bf16_block(ar, wf + (size_t)nb * kbn * 64 + lane, kbn);
-      const int col = nb * 32 + lane % 32;
+      floatx16 c0, c1;
+      mfma_bf16_pair(ar0, ar1, wf + (size_t)nb * kbn * 64, kbn, c0, c1);
+      const int col = nb * 32 + li;
+      const float bb = b2[col], ww = w3[col];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        H2[row * H + col] = fmaxf(c[r] + b2[col], 0.f);
+        p0[r] = fmaf(fmaxf(c0[r] + bb, 0.f), ww, p0[r]);
+        p1[r] = fmaf(fmaxf(c1[r] + bb, 0.f), ww, p1[r]);
       }
+    }
+    const float s0 = rows_of_block(p0, lane);
+    const float s1 = rows_of_block(p1, lane);
+    if ((lane & 1) == 0) {
+      const int r = li >> 1;
+      const int row = 8 * (r / 4) + 4 * lk + (r % 4);
+      ypart[wave * kInferRows + row] = s0;
+      ypart[wave * kInferRows + 32 + row] = s1;
     }
   }
   __syncthreads();
-  // layer 3: y = H2 w3 + b3, eight lanes per row
-  {
-    const int r = tid / 8, part = tid % 8;
-    float s = 0.f;
-    for (int i = part; i < H; i += 8) s = fmaf(w3[i], H2[r * H + i], s);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    if (part == 0 && row0 + r < n) y[blockIdx.y * y_run_stride + row0 + r] = s + b3;
+  if (tid < kInferRows && row0 + tid < n) {
+    float s = b3;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) s += ypart[w * kInferRows + tid];
+    y[blockIdx.y * y_run_stride + row0 + tid] = s;
   }
 }
 
@@ -1070,7 +1132,9 @@ de_status one_generation(de_sur* s, hipStream_t st) {
   SurArgs a = args_of(s);
   a.use_model = (s->sp.k > 1 && s->gen >= s->sp.warmup_gens) ? 1 : 0;
   s->last_use_model = a.use_model;
-  hipLaunchKernelGGL(de::k_sur_cand, dim3((a.NP * a.k + 3) / 4, a.runs),
+  const int per_wg = 4 * de::cand_rows_per_wave(a.D);
+  hipLaunchKernelGGL(de::k_sur_cand,
+                     dim3((a.NP * a.k + per_wg - 1) / per_wg, a.runs),
                      dim3(256), 0, st, a);
   de_status rc = FROM_HIP(hipGetLastError());
   if (rc != DE_OK) return rc;
@@ -1083,10 +1147,6 @@ de_status one_generation(de_sur* s, hipStream_t st) {
                        (const float*)a.cand, (size_t)rows * a.ldx, rows, a.ldx,
                        a.pred, (size_t)rows, 0);
     rc = FROM_HIP(hipGetLastError());
-    if (rc != DE_OK) return rc;
-  } else {
-    rc = FROM_HIP(hipMemsetAsync(a.pred, 0,
-                                 4 * (size_t)a.runs * a.NP * a.k, st));
     if (rc != DE_OK) return rc;
   }
   hipLaunchKernelGGL(de::k_sur_select,
