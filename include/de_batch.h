@@ -86,7 +86,7 @@ typedef struct de_batch_params {
  *   DE_BATCH_TILE64 : 64 trial rows per tile, 256 threads; D padded to a
  *                     multiple of 32; one MFMA K-step per LDS read.
  *   DE_BATCH_TILE32 : 32 rows per tile, 256 threads, same padding.
- *   DE_BATCH_WIDE   : 64 rows per tile, 512 threads, D padded to a multiple
+ *   DE_BATCH_WIDE   : 64 rows per tile, 1024 threads, D padded to a multiple
  *                     of 128, software-pipelined MFMA loop (the kernel of
  *                     de.h's BF16 path).                                    */
 enum {

@@ -14,7 +14,7 @@
 //                     threads (one Philox block and one float4 per item),
 //                     so small D keeps every lane busy; D padded to 32; one
 //                     MFMA per LDS read.
-//   k_bt_wide         the per-problem BF16 tile (64 rows, 512 threads, D
+//   k_bt_wide         the per-problem BF16 tile (64 rows, 1024 threads, D
 //                     padded to 128, software-pipelined MFMA loop).
 // An autotuner times each variant on each dimension's runs and keeps the
 // fastest; a generation is then one launch per variant in use, and chunks
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_bt_rot(BatchArgs b) {
 // balances them; a tile loop here would keep lane addresses live across
 // tiles and spill).
 template <bool EVAL>
-__global__ __launch_bounds__(512) void k_bt_wide(BatchArgs b) {
+__global__ __launch_bounds__(kRotBf16Threads) void k_bt_wide(BatchArgs b) {
   const long long gen = batch_gen(b);
   const int par = (int)(gen & 1);
   {
@@ -358,8 +358,8 @@ __global__ __launch_bounds__(512) void k_bt_wide(BatchArgs b) {
     a.key_lo = b.key_lo;
     a.key_hi = b.key_hi;
     a.run_base = (uint32_t)tile.run;
-    rot_tile<PrecBF16, 64, 512, EVAL>(a, 0, tile.row0,
-                                      min(64, rn.NP - tile.row0));
+    rot_tile<PrecBF16, 64, kRotBf16Threads, EVAL>(
+        a, 0, tile.row0, min(64, rn.NP - tile.row0));
   }
 }
 
@@ -461,7 +461,8 @@ const Variant& variant(int v) {
        reinterpret_cast<const void*>(&de::k_bt_rot<64, 256, true>)},
       {32, 256, reinterpret_cast<const void*>(&de::k_bt_rot<32, 256, false>),
        reinterpret_cast<const void*>(&de::k_bt_rot<32, 256, true>)},
-      {64, 512, reinterpret_cast<const void*>(&de::k_bt_wide<false>),
+      {64, de::kRotBf16Threads,
+       reinterpret_cast<const void*>(&de::k_bt_wide<false>),
        reinterpret_cast<const void*>(&de::k_bt_wide<true>)},
   };
   return kVariants[v];
@@ -471,7 +472,9 @@ size_t variant_lds(int v, int D) {
   switch (v) {
     case DE_BATCH_TILE64: return de::bt_lds_bytes<64, 256>(dpad_generic(D));
     case DE_BATCH_TILE32: return de::bt_lds_bytes<32, 256>(dpad_generic(D));
-    default: return de::rot_lds_bytes_host(de::kPrecBF16, dpad_wide(D));
+    default:
+      return de::rot_lds_bytes<de::PrecBF16, 64, de::kRotBf16Threads>(
+          dpad_wide(D));
   }
 }
 

@@ -418,26 +418,29 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+constexpr int kBf16Threads = kRotBf16Threads;
+
 template <bool EVAL>
 hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
   if (!EVAL && a.jde) {
     if (prec != kPrecBF16)
       return launch_rot_t<PrecF32, 32, 512, false, true>(a, s);
-    return launch_rot_t<PrecBF16, 64, 512, false, true>(a, s);
+    return launch_rot_t<PrecBF16, 64, kBf16Threads, false, true>(a, s);
   }
   if (prec != kPrecBF16) return launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
-  return launch_rot_t<PrecBF16, 64, 512, EVAL>(a, s);
+  return launch_rot_t<PrecBF16, 64, kBf16Threads, EVAL>(a, s);
 }
 
 }  // namespace
 
-// LDS bytes of the rotated kernel: BF16 tiles of 64 rows, FP32 tiles of 32
-// rows, both 512 threads.
+// LDS bytes of the rotated kernel: BF16 tiles of 64 rows and 1024 threads,
+// FP32 tiles of 32 rows and 512 threads.
 size_t rot_lds_bytes_host(int prec, int dpad, bool jde) {
   if (jde)
-    return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, 512, true>(dpad)
-                             : rot_lds_bytes<PrecF32, 32, 512, true>(dpad);
-  return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, 512>(dpad)
+    return prec == kPrecBF16
+               ? rot_lds_bytes<PrecBF16, 64, kBf16Threads, true>(dpad)
+               : rot_lds_bytes<PrecF32, 32, 512, true>(dpad);
+  return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, kBf16Threads>(dpad)
                            : rot_lds_bytes<PrecF32, 32, 512>(dpad);
 }
 

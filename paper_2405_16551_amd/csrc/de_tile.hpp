@@ -117,34 +117,53 @@ __device__ __forceinline__ void osc_accumulate(floatx16& part,
 // 256-coordinate chunks per producer step (rows per step: 8 / this).  One
 // chunk of eight rows measured fastest at D = 1000 (BF16 and FP32 tiles).
 constexpr int kProducerChunks = 1;
+// Rows per producer step of 1024-thread tiles (128 registers per lane).
+constexpr int kRows1024 = 4;
+// Threads of the BF16 rotated tile: 16 waves, four per SIMD, measured
+// faster at D = 1000 than 8 waves with twice the registers each (more
+// waves in flight for the producer's loads and the MFMA loop's L2 reads).
+constexpr int kRotBf16Threads = 1024;
 
 // R fragments of four consecutive K-steps for two column blocks.
 struct BFrags {
   bf16x8 b0[4], b1[4];
 };
 
+template <int NBW = 2>
 __device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
                                             const bf16x8* rb1, int kb) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     f.b0[u] = rb0[(size_t)(kb + u) * 64];
-    f.b1[u] = rb1[(size_t)(kb + u) * 64];
+    if constexpr (NBW == 2) f.b1[u] = rb1[(size_t)(kb + u) * 64];
   }
 }
 
 // Scheduling pattern for one K-step: its LDS reads (next A fragments) and
 // L2 loads (R fragments of a later step) are placed between its MFMAs
 // instead of in one burst, so the matrix unit keeps busy while they go out.
-template <int MB>
+template <int MB, int NBW = 2>
 __device__ __forceinline__ void interleave_step() {
-  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-  __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
-  if constexpr (MB == 2) {
+  if constexpr (NBW == 2) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+    if constexpr (MB == 2) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+  } else {
+    // one column block: per row block one MFMA and its next A read, then
+    // the step's R load
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    if constexpr (MB == 2) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
     __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -176,7 +195,11 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   constexpr int MB = BM / 32;
   constexpr int kRotThreads = NT;
   constexpr int kRotWaves = NT / 64;
+  // 1024-thread tiles (four waves per SIMD, 128 registers each): one
+  // column block per wave and pass, four producer rows per step
+  constexpr int NBW = NT >= 1024 ? 1 : 2;
   static_assert(MB == 1 || (MB == 2 && sizeof(T) == 2), "tile shape");
+  static_assert(NBW == 2 || sizeof(T) == 2, "FP32 tiles use two blocks");
   extern __shared__ __align__(16) char smem[];
   const int dpad = a.dpad;
   const int stride = dpad + P::kPad;
@@ -232,7 +255,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     // past the wave's last go to its last row (values unused), so no load
     // sits behind a per-lane branch.
     constexpr int CG = kProducerChunks;
-    constexpr int RB = 8 / CG;
+    constexpr int RB = (NT >= 1024 ? kRows1024 : 8) / CG;
     const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
     const int dlast = ((a.D + 3) / 4 - 1) * 4;
     for (int t0 = 0; t0 < tq; t0 += CG) {
@@ -339,7 +362,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   // time, so concurrent requests from the CUs of an XCD share L2 lines.
   const int nblk = dpad / 32;
   floatx16 part0 = {}, part1 = {};
-  for (int nb0 = wave * 2; nb0 < nblk; nb0 += kRotWaves * 2) {
+  for (int nb0 = wave * NBW; nb0 < nblk; nb0 += kRotWaves * NBW) {
     floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
     if constexpr (sizeof(T) == 2) {
       // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per
@@ -360,7 +383,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       BFrags fa, fb;
       a0s[0] = *reinterpret_cast<const bf16x8*>(ar);
       if constexpr (MB == 2) a1s[0] = *reinterpret_cast<const bf16x8*>(ar1);
-      load_bfrags(fa, rb0, rb1, 0);
+      load_bfrags<NBW>(fa, rb0, rb1, 0);
       for (int kb = 0; kb < kbn; kb += 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -373,24 +396,28 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
           }
           if (u < 4) {
             fb.b0[u] = rb0[(size_t)(kb + 4 + u) * 64];
-            fb.b1[u] = rb1[(size_t)(kb + 4 + u) * 64];
+            if constexpr (NBW == 2) fb.b1[u] = rb1[(size_t)(kb + 4 + u) * 64];
           } else if (kb + 8 < kbn) {
             fa.b0[u - 4] = rb0[(size_t)(kb + 8 + u - 4) * 64];
-            fa.b1[u - 4] = rb1[(size_t)(kb + 8 + u - 4) * 64];
+            if constexpr (NBW == 2)
+              fa.b1[u - 4] = rb1[(size_t)(kb + 8 + u - 4) * 64];
           }
           const bf16x8 b0 = u < 4 ? fa.b0[u & 3] : fb.b0[u & 3];
-          const bf16x8 b1 = u < 4 ? fa.b1[u & 3] : fb.b1[u & 3];
           c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b0, c00, 0, 0,
                                                         0);
-          c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b1, c01, 0, 0,
-                                                        0);
+          if constexpr (NBW == 2) {
+            const bf16x8 b1 = u < 4 ? fa.b1[u & 3] : fb.b1[u & 3];
+            c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b1, c01, 0,
+                                                          0, 0);
+            if constexpr (MB == 2)
+              c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b1, c11,
+                                                            0, 0, 0);
+          }
           if constexpr (MB == 2) {
             c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b0, c10, 0,
                                                           0, 0);
-            c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b1, c11, 0,
-                                                          0, 0);
           }
-          interleave_step<MB>();
+          interleave_step<MB, NBW>();
         }
       }
     } else {
@@ -418,10 +445,10 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     }
     constexpr bool kFastSin = sizeof(T) == 2;
     osc_accumulate<kFastSin>(part0, c00);
-    osc_accumulate<kFastSin>(part0, c01);
+    if constexpr (NBW == 2) osc_accumulate<kFastSin>(part0, c01);
     if constexpr (MB == 2) {
       osc_accumulate<kFastSin>(part1, c10);
-      osc_accumulate<kFastSin>(part1, c11);
+      if constexpr (NBW == 2) osc_accumulate<kFastSin>(part1, c11);
     }
   }
   // 32x32 accumulator layout: register r of lane l holds row
