@@ -215,3 +215,63 @@ def test_control_calls_need_a_jde_handle():
     f = (ctypes.c_float * 4)()
     assert d._lib.de_get_control(None, None, f, f) == d.DE_E_STATE
     assert d._lib.de_set_control(None, None, f, f) == d.DE_E_STATE
+
+
+# --------------------------------------------------------------------------
+# Surrogate-assisted variant (include/de_surrogate.h): checks are synchronous
+# and precede any device access.
+
+def _sur(**kw):
+    base = dict(d.SURROGATE_DEFAULTS)
+    base.update(kw)
+    return d.de_surrogate_params(*[base[f] for f, _ in
+                                   d.de_surrogate_params._fields_])
+
+
+def _comp(n=8, ldr=100, sigma=50.0, reserved=0, bias_val=0.0):
+    bias = (ctypes.c_float * n)(*([bias_val] * n))
+    c = d.de_composition(n, ldr, sigma, reserved, 256, 512, bias)
+    c._keep = bias
+    return c
+
+
+def sur_status(p, c, s):
+    n = ctypes.c_size_t(0)
+    return d._lib.de_sur_workspace_bytes(ctypes.byref(p), ctypes.byref(c),
+                                         ctypes.byref(s), ctypes.byref(n)), n.value
+
+
+def test_surrogate_workspace_and_model_size():
+    p = P(runs=30, NP=512, D=100)
+    st, n = sur_status(p, _comp(), _sur())
+    assert st == d.DE_OK and n > 0
+    assert d._lib.de_sur_model_size(100, 256) == 256 * 100 + 256 * 256 + 3 * 256 + 1
+    # more runs need more workspace
+    assert sur_status(P(runs=31, NP=512, D=100), _comp(), _sur())[1] > n
+
+
+@pytest.mark.parametrize("skw", [
+    dict(k=0), dict(k=17), dict(hidden=48), dict(hidden=512), dict(batch=48),
+    dict(batch=2048), dict(archive=100), dict(steps=-1), dict(warmup_gens=-1),
+    dict(lr=0.0), dict(lr=math.nan), dict(beta1=1.0), dict(beta2=-0.1),
+    dict(eps=0.0)])
+def test_invalid_surrogate_settings_rejected(skw):
+    assert sur_status(P(runs=2, NP=512, D=100), _comp(), _sur(**skw))[0] == d.DE_E_INVAL
+
+
+@pytest.mark.parametrize("ckw", [
+    dict(n=0), dict(n=65), dict(ldr=99), dict(sigma=0.0), dict(sigma=math.inf),
+    dict(reserved=1), dict(bias_val=math.nan)])
+def test_invalid_composition_rejected(ckw):
+    assert sur_status(P(runs=2, NP=512, D=100), _comp(**ckw), _sur())[0] == d.DE_E_INVAL
+
+
+def test_surrogate_calls_on_missing_handles():
+    f = (ctypes.c_float * 4)()
+    g = ctypes.c_int64()
+    assert d._lib.de_sur_generation(None, 1, None) == d.DE_E_STATE
+    assert d._lib.de_sur_read(None, None, None, None, None) == d.DE_E_STATE
+    assert d._lib.de_sur_get_generation(None, ctypes.byref(g)) == d.DE_E_STATE
+    assert d._lib.de_sur_get_model(None, None, f, f, f, None) == d.DE_E_STATE
+    assert d._lib.de_sur_train(None, 1, None) == d.DE_E_STATE
+    assert d._lib.de_sur_destroy(None) == d.DE_E_STATE
