@@ -9,7 +9,9 @@
 //
 //   k_sep   separable objective (shifted sphere).  A group of LPI lanes owns
 //           one individual; each lane owns 4 consecutive coordinates per
-//           step (one Philox block, one float4 of each row).  HBM-bound.
+//           step (one Philox block, one float4 of each row).  Rows of more
+//           than 256 coordinates take k_sep_row (one wave per row, donors
+//           drawn once per workgroup, scalar row pointers).
 //   k_rot   rotated objective z = R (x - o), f = sum z^2 + sin^2(3z).  A
 //           workgroup owns a tile of BM trial rows: it builds them into LDS
 //           as the A operand, runs Z = Y R^T on MFMA with the objective and
@@ -18,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 
@@ -357,6 +360,140 @@ __global__ __launch_bounds__(256) void k_debug_draws(GenArgs a, int* idx4,
 // ---------------------------------------------------------------------------
 // Launchers.
 
+// ---------------------------------------------------------------------------
+// Separable objective, one wave per row, rows of more than 256 coordinates
+// (ITER float4 per lane).  The work per row is mostly VALU, so this form
+// trims instructions without changing any result:
+//   - wave 0 draws the donors (and jDE controls) of the workgroup's four
+//     rows in four lanes and hands them over in LDS (one Philox block per
+//     four rows instead of one per row); the other waves issue their target
+//     and shift loads meanwhile;
+//   - row pointers are wave-uniform, so loads take a scalar base and one
+//     32-bit lane offset;
+//   - the crossover test compares the raw word with a precomputed bound:
+//     (w >> 8) <= t  <=>  w <= t * 256 + 255 (every word when t = 2^24);
+//   - the end-of-row checks run only on the chunk that holds the end.
+template <int ITER, bool JDE>
+__global__ __launch_bounds__(256) void k_sep_row(GenArgs a) {
+  __shared__ int sd[4][4];
+  __shared__ Control sc[4];
+  const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+  const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+  const int g0 = lb * 4;
+  if (wave == 0 && lane < 4 && g0 + lane < a.nrows) {
+    const int gl = g0 + lane;
+    const int run = gl / a.NP, i = gl - run * a.NP;
+    const Donors d =
+        pick_donors((uint32_t)run, a.gen, i, a.NP, a.D, a.key_lo, a.key_hi);
+    sd[lane][0] = d.r1;
+    sd[lane][1] = d.r2;
+    sd[lane][2] = d.r3;
+    sd[lane][3] = d.jrand;
+    if constexpr (JDE) {
+      const float2 c = a.jp_cur[gl];
+      sc[lane] = jde_control((uint32_t)run, a.gen, i, a.key_lo, a.key_hi,
+                             a.jF_lo, a.jF_span, a.jtau_F, a.jtau_CR,
+                             Control{c.x, c.y});
+    }
+  }
+  const int g = __builtin_amdgcn_readfirstlane(g0 + wave);
+  const bool live = g < a.nrows;
+  const int run = live ? g / a.NP : 0, i = live ? g - run * a.NP : 0;
+  const int dlast = ((a.D + 3) / 4 - 1) * 4;
+  const float* xrow = a.pop_cur + (size_t)(live ? g : 0) * a.ldx;
+  float4 xv[ITER], v1[ITER], v2[ITER], v3[ITER], ov[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t jl = (uint32_t)min(4 * (lane + 64 * it), dlast);
+    xv[it] = ld4(xrow + jl);
+    ov[it] = ld4(a.o + jl);
+  }
+  float fx = 0.f;
+  int chg = 0;
+  if (live) {
+    fx = a.fit_cur[g];
+    chg = a.changed[g];
+  }
+  __syncthreads();
+  if (!live) return;  // wave-uniform, after the only barrier
+  const int r1 = __builtin_amdgcn_readfirstlane(sd[wave][0]);
+  const int r2 = __builtin_amdgcn_readfirstlane(sd[wave][1]);
+  const int r3 = __builtin_amdgcn_readfirstlane(sd[wave][2]);
+  const int jrand = __builtin_amdgcn_readfirstlane(sd[wave][3]);
+  float F = a.F;
+  uint32_t crt = a.cr_threshold;
+  Control ctl{0.f, 0.f};
+  if constexpr (JDE) {
+    ctl = sc[wave];
+    F = ctl.F;
+    crt = cr_threshold_of(ctl.CR);
+  }
+  const uint32_t wmax = crt >= (1u << 24) ? 0xFFFFFFFFu : (crt << 8) | 0xFFu;
+  const float* base = a.pop_cur + (size_t)run * a.NP * a.ldx;
+  const float* x1 = base + (size_t)r1 * a.ldx;
+  const float* x2 = base + (size_t)r2 * a.ldx;
+  const float* x3 = base + (size_t)r3 * a.ldx;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t jl = (uint32_t)min(4 * (lane + 64 * it), dlast);
+    v1[it] = ld4(x1 + jl);
+    v2[it] = ld4(x2 + jl);
+    v3[it] = ld4(x3 + jl);
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int q = lane + 64 * it, j0 = 4 * q;
+    const Words4 w = draw_block(kTagXover, (uint32_t)run, a.gen, (uint32_t)i,
+                                (uint32_t)q, a.key_lo, a.key_hi);
+    float4 u = xv[it];
+    if (256 * (it + 1) <= a.D) {
+      // every coordinate of this chunk lies inside the row
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool tk = (w.w[c] <= wmax) || (j0 + c == jrand);
+        const float mv = mutant_coord(get(v1[it], c), get(v2[it], c),
+                                      get(v3[it], c), F, a.lo, a.hi);
+        set(u, c, tk ? mv : get(xv[it], c));
+        const float y = get(u, c) - get(ov[it], c);
+        acc = fmaf(y, y, acc);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool in = j0 + c < a.D;
+        const bool tk = in && ((w.w[c] <= wmax) || (j0 + c == jrand));
+        const float mv = mutant_coord(get(v1[it], c), get(v2[it], c),
+                                      get(v3[it], c), F, a.lo, a.hi);
+        set(u, c, tk ? mv : get(xv[it], c));
+        const float y = get(u, c) - get(ov[it], c);
+        acc = in ? fmaf(y, y, acc) : acc;
+      }
+    }
+    v1[it] = u;  // the trial chunk replaces the first donor's
+  }
+  const float f = group_sum<64>(acc);
+  const bool accept = f < fx;
+  // a rejected row is rewritten only if the other buffer holds a stale copy
+  if (accept || chg != 0) {
+    float* nrow = a.pop_next + (size_t)g * a.ldx;
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int j0 = 4 * (lane + 64 * it);
+      if (j0 < a.D) st4(nrow + j0, accept ? v1[it] : xv[it]);
+    }
+  }
+  if (lane == 0) {
+    a.fit_next[g] = accept ? f : fx;
+    a.changed[g] = accept ? 1 : 0;
+    if constexpr (JDE) {
+      // the trial's F', CR' survive only with the trial
+      a.jp_next[g] = accept ? make_float2(ctl.F, ctl.CR) : a.jp_cur[g];
+    }
+    if (accept) record_accept(a, run, i, f);
+  }
+}
+
 namespace {
 
 int grid_for(size_t work, int per_block) {
@@ -375,9 +512,24 @@ hipError_t launch_sep_t(const GenArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int ITER, bool JDE>
+hipError_t launch_sep_row_t(const GenArgs& a, hipStream_t s) {
+  const int blocks = (a.nrows + 3) / 4;
+  hipLaunchKernelGGL((k_sep_row<ITER, JDE>), dim3(blocks), dim3(256), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
 template <bool EVAL, bool JDE>
 hipError_t launch_sep_j(const GenArgs& a, hipStream_t s) {
   const int nq = (a.D + 3) / 4;
+  if (!EVAL && nq > 64) {
+    if (nq <= 128) return launch_sep_row_t<2, JDE>(a, s);
+    if (nq <= 256) return launch_sep_row_t<4, JDE>(a, s);
+    if (nq <= 512) return launch_sep_row_t<8, JDE>(a, s);
+    if (nq <= 1024) return launch_sep_row_t<16, JDE>(a, s);
+    return hipErrorInvalidValue;
+  }
   if (nq <= 4) return launch_sep_t<4, 1, EVAL, JDE>(a, s);
   if (nq <= 8) return launch_sep_t<8, 1, EVAL, JDE>(a, s);
   if (nq <= 16) return launch_sep_t<16, 1, EVAL, JDE>(a, s);

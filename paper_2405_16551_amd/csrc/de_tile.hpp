@@ -267,13 +267,18 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
         float4 xv[RB][CG], v1[RB][CG], v2[RB][CG], v3[RB][CG];
 #pragma unroll
         for (int h = 0; h < RB; ++h) {
-          const int rl = wave + kRotWaves * min(k + h, nrow_w - 1);
+          // row and donor indices are wave-uniform: scalar row pointers
+          const int rl = __builtin_amdgcn_readfirstlane(
+              wave + kRotWaves * min(k + h, nrow_w - 1));
           const float* xrow = base + (size_t)(row0 + rl) * a.ldx;
           const float *x1 = xrow, *x2 = xrow, *x3 = xrow;
           if (!EVAL) {
-            x1 = base + (size_t)donors[rl * 4 + 0] * a.ldx;
-            x2 = base + (size_t)donors[rl * 4 + 1] * a.ldx;
-            x3 = base + (size_t)donors[rl * 4 + 2] * a.ldx;
+            x1 = base + (size_t)__builtin_amdgcn_readfirstlane(
+                            donors[rl * 4 + 0]) * a.ldx;
+            x2 = base + (size_t)__builtin_amdgcn_readfirstlane(
+                            donors[rl * 4 + 1]) * a.ldx;
+            x3 = base + (size_t)__builtin_amdgcn_readfirstlane(
+                            donors[rl * 4 + 2]) * a.ldx;
           }
 #pragma unroll
           for (int u = 0; u < CG; ++u) {

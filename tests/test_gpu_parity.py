@@ -92,6 +92,13 @@ def test_debug_draws_bit_exact(runs, NP, D, CR):
     ("sphere", "fp32", 1, 64, 10, 0.9),
     ("sphere", "fp32", 2, 70, 1000, 0.9),
     ("sphere", "fp32", 2, 4, 1, 0.5),
+    # one-wave-per-row form: rows of 257..512, 513..1024 (last chunk
+    # partial), 1025..2048 and 2049..4096 coordinates; row counts that leave
+    # workgroups partly empty; CR = 1 takes every coordinate
+    ("sphere", "fp32", 3, 45, 300, 0.9),
+    ("sphere", "fp32", 1, 33, 513, 0.7),
+    ("sphere", "fp32", 1, 22, 1500, 1.0),
+    ("sphere", "fp32", 1, 9, 3001, 0.3),
     ("rot_osc", "fp32", 2, 70, 100, 0.9),
     ("rot_osc", "fp32", 1, 40, 13, 0.3),
     ("rot_osc", "fp32", 1, 65, 250, 0.9),
