@@ -13,7 +13,9 @@ generations).  Also reported: generations per second, the roofline
 position of the generation kernel (HIP events around the K launches,
 algorithmic FLOPs 2 D^2 per trial), a separable companion workload
 (shifted sphere, same sizes; HBM roofline), wall time to the 1e-8 target
-on the small sphere workload (Section 7.3.4 early stopping), a batch of 512
+on the small sphere workload (Section 7.3.4 early stopping), wall time to
+the FP64 oracle's median final best on the rotated D = 100 workload (64
+runs, with the oracle's own time to it extrapolated), a batch of 512
 independent runs of mixed NP, D, F and CR advanced by graph replays, and
 the FP64 CPU oracle timed on a bounded sample of the headline workload.
 """
@@ -350,6 +352,75 @@ def time_to_target(target=1e-8, max_gens=5000, check_every=50):
                 check_every=check_every)
 
 
+def time_to_target_c2(with_oracle, max_gens=6000, check_every=50):
+    """Rotated D = 100, 64 runs x NP 256, FP32 product: wall time until half
+    of the runs reach the FP64 oracle's median best after 3000 generations
+    (the value tests/golden/make_c2_reference.py stores).  The GPU side is
+    one de_evolve call; the time until half of the runs have hit is that
+    call's wall time per generation times the generation at which the
+    (n/2)-th run first hit.
+    With with_oracle, the oracle's time to the same point is extrapolated
+    from a timed sample of its generations on the host cores."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2405_16551_amd import instances
+    from paper_2405_16551_amd.de import DifferentialEvolution
+
+    with open(os.path.join(ROOT, "tests", "golden",
+                           "oracle_c2_distribution.json")) as f:
+        ref = json.load(f)
+    c = ref["config"]
+    target = ref["median_final_best"]
+    o, R = instances.make_instance(c["kind"], c["D"], c["obj_seed"])
+    de = DifferentialEvolution(runs=c["runs"], NP=c["NP"], D=c["D"], F=c["F"],
+                               CR=c["CR"], seed=c["seed"], kind=c["kind"],
+                               o=o, R=R, gemm_prec="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, hits = de.evolve(max_gens, target=target, check_every=check_every)
+    t = time.perf_counter() - t0
+    de.close()
+
+    def half_hit(v):
+        # generation by which half of the runs have reached the target (the
+        # n/2-th smallest first-hit generation; never reached = infinity)
+        h = np.sort(np.array([x if x >= 0 else np.inf for x in v],
+                             dtype=np.float64))
+        m = float(h[(len(h) + 1) // 2 - 1])
+        return (m if np.isfinite(m) else None), int(np.isfinite(h).sum())
+
+    gmed, ghit = half_hit(hits)
+    out = dict(
+        workload=(f"DE/rand/1/bin, {c['runs']} runs x NP={c['NP']}, "
+                  f"D={c['D']}, rotated oscillating, fp32 rotation product"),
+        target=target,
+        target_source=("median over the runs of the FP64 oracle's best after "
+                       f"{c['G']} generations (same seeds and instance)"),
+        generations_run=done, seconds=round(t, 4), check_every=check_every,
+        runs_at_target=ghit, generation_half_at_target=gmed,
+        seconds_to_half_at_target=(round(gmed * t / done, 4) if gmed
+                                   else None))
+    if with_oracle:
+        omed, _ = half_hit(ref["oracle_first_gen_at_target"])
+        threads = oracle.max_threads()
+        ng = 10
+        t1 = time.perf_counter()
+        oracle.run(runs=c["runs"], NP=c["NP"], D=c["D"], F=c["F"], CR=c["CR"],
+                   lo=c["lo"], hi=c["hi"], seed=c["seed"],
+                   kind=oracle.OBJ_ROT_OSC, o=o, R=R, G=ng, nthreads=threads)
+        per_gen = (time.perf_counter() - t1) / ng
+        out["oracle"] = dict(
+            generation_half_at_target=omed, cores=threads,
+            seconds_per_generation=round(per_gen, 4),
+            seconds_to_half_at_target=(round(omed * per_gen, 2) if omed
+                                       else None),
+            sample=f"{ng} generations of all {c['runs']} runs in FP64, "
+                   "extrapolated")
+    return out
+
+
 def cpu_baseline(name, budget_s=15.0):
     """The FP64 oracle on the host cores, one generation of one run of the
     workload (NP trials), repeated while the budget lasts."""
@@ -469,6 +540,8 @@ def main():
         line["batched"] = time_batch(max(64, args.steps // 4), args.warmup)
         line["surrogate"] = time_surrogate()
         line["time_to_target"] = time_to_target()
+        line["time_to_target_c2"] = time_to_target_c2(
+            with_oracle=not args.no_cpu_baseline)
         line["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)

@@ -42,7 +42,7 @@ def make_jde(**kw):
 
 @pytest.mark.parametrize("kind,prec,runs,NP,D", [
     ("sphere", "fp32", 3, 50, 37), ("sphere", "fp32", 2, 4, 1),
-    ("sphere", "fp32", 3, 45, 600),
+    ("sphere", "fp32", 3, 45, 600), ("sphere", "fp32", 2, 30, 1500),
     ("rot_osc", "fp32", 2, 70, 100), ("rot_osc", "bf16", 2, 130, 100),
 ])
 def test_jde_generation_matches_oracle(kind, prec, runs, NP, D):

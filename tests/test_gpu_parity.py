@@ -15,6 +15,7 @@ arithmetic of each path):
     1e-8 success threshold of Section 7.3.4.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -321,6 +322,29 @@ def test_best_distribution_over_30_runs(kind, prec, NP, D, G, checks):
                                                  res["best_trace"][:, c])
         assert ok, (c, pu, pks, np.median(gpu[c]),
                     np.median(res["best_trace"][:, c]))
+
+
+def test_c2_distribution_full_size():
+    # 64 runs x NP 256, D 100, rotated, FP32 product, 3000 generations: the
+    # GPU's best over the runs at every checkpoint against the FP64
+    # oracle's stored distribution (tests/golden/make_c2_reference.py)
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "oracle_c2_distribution.json")) as f:
+        gold = json.load(f)
+    c = gold["config"]
+    de, o, R = make_de(runs=c["runs"], NP=c["NP"], D=c["D"], F=c["F"],
+                       CR=c["CR"], seed=c["seed"], kind=c["kind"],
+                       gemm_prec="fp32")
+    done = 0
+    for g in gold["checkpoints"]:
+        de.generation(g - done)
+        done = g
+        gpu = np.array(de.stats()[1])
+        ok, pu, pks = de_stats.same_distribution(gpu, gold["best"][str(g)])
+        print(f"c2 gen {g}: gpu median {np.median(gpu):.4e} oracle median "
+              f"{np.median(gold['best'][str(g)]):.4e} p_U {pu:.3f} p_KS {pks:.3f}")
+        assert ok, (g, pu, pks)
 
 
 # ---------------------------------------------------------------------------

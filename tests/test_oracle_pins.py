@@ -465,6 +465,26 @@ def test_oracle_regression_fixture():
             for i in range(4)] == gold["draws_seed1_np64_d10"]
 
 
+def test_c2_distribution_fixture_prefix():
+    # the stored 64-run distribution (tests/golden/make_c2_reference.py) is
+    # the oracle's own: its first checkpoint is reproduced bit for bit, and
+    # the stored medians fall generation by generation
+    import json
+    with open(os.path.join(HERE, "golden", "oracle_c2_distribution.json")) as f:
+        gold = json.load(f)
+    c = gold["config"]
+    o, R = instances.make_instance(c["kind"], c["D"], c["obj_seed"])
+    g0 = gold["checkpoints"][0]
+    res = oracle.run(runs=c["runs"], NP=c["NP"], D=c["D"], F=c["F"],
+                     CR=c["CR"], lo=c["lo"], hi=c["hi"], seed=c["seed"],
+                     kind=1, o=o, R=R, G=g0, nthreads=8)
+    assert [float(v) for v in res["best_trace"][:, g0]] == gold["best"][str(g0)]
+    med = [np.median(gold["best"][str(g)]) for g in gold["checkpoints"]]
+    assert all(b < a for a, b in zip(med, med[1:]))
+    assert gold["median_final_best"] == np.median(
+        gold["best"][str(c["G"])])
+
+
 # --------------------------------------------------------------------------
 # jDE (control parameters adapted per individual; Section 2's list of DE
 # variants, Section 8.2).  The adaptation constants come from Brest et al.
