@@ -373,8 +373,12 @@ __global__ __launch_bounds__(256) void k_debug_draws(GenArgs a, int* idx4,
 //   - the crossover test compares the raw word with a precomputed bound:
 //     (w >> 8) <= t  <=>  w <= t * 256 + 255 (every word when t = 2^24);
 //   - the end-of-row checks run only on the chunk that holds the end.
+// Rows of up to 1024 coordinates fit in 96 registers: five waves per SIMD
+// (one more than the compiler picks unasked) keep more loads in flight.
 template <int ITER, bool JDE>
-__global__ __launch_bounds__(256) void k_sep_row(GenArgs a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(ITER <= 4 ? 5 : 1)))
+void k_sep_row(GenArgs a) {
   __shared__ int sd[4][4];
   __shared__ Control sc[4];
   const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
