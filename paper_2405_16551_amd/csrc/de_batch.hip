@@ -320,9 +320,13 @@ __global__ __launch_bounds__(NT) void k_bt_rot(BatchArgs b) {
 // Wide variant: the per-problem BF16 tile with the run's own arguments, one
 // workgroup per tile (its tiles are long enough that the dispatcher's order
 // balances them; a tile loop here would keep lane addresses live across
-// tiles and spill).
-template <bool EVAL>
-__global__ __launch_bounds__(kRotBf16Threads) void k_bt_wide(BatchArgs b) {
+// tiles and spill).  NT follows the padded width as in the per-problem
+// kernel (two 512-thread workgroups per CU up to 512, else one of 1024), so
+// the results equal a per-problem handle's bit for bit.
+template <bool EVAL, int NT>
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(NT < 1024 ? 4 : 1)))
+void k_bt_wide(BatchArgs b) {
   const long long gen = batch_gen(b);
   const int par = (int)(gen & 1);
   {
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(kRotBf16Threads) void k_bt_wide(BatchArgs b) {
     a.key_lo = b.key_lo;
     a.key_hi = b.key_hi;
     a.run_base = (uint32_t)tile.run;
-    rot_tile<PrecBF16, 64, kRotBf16Threads, EVAL>(
+    rot_tile<PrecBF16, 64, NT, EVAL>(
         a, 0, tile.row0, min(64, rn.NP - tile.row0));
   }
 }
@@ -449,32 +453,48 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int dpad_generic(int D) { return (int)round_up((size_t)D, 32); }
 int dpad_wide(int D) { return (int)round_up((size_t)D, 128); }
 
-struct Variant {
+// Kernels of a variant: tile rows, threads, generation and evaluation form.
+struct Kern {
   int bm, nt;
   const void* gen_fn;
   const void* eval_fn;
 };
 
-const Variant& variant(int v) {
-  static const Variant kVariants[DE_BATCH_NVARIANTS] = {
-      {64, 256, reinterpret_cast<const void*>(&de::k_bt_rot<64, 256, false>),
-       reinterpret_cast<const void*>(&de::k_bt_rot<64, 256, true>)},
-      {32, 256, reinterpret_cast<const void*>(&de::k_bt_rot<32, 256, false>),
-       reinterpret_cast<const void*>(&de::k_bt_rot<32, 256, true>)},
-      {64, de::kRotBf16Threads,
-       reinterpret_cast<const void*>(&de::k_bt_wide<false>),
-       reinterpret_cast<const void*>(&de::k_bt_wide<true>)},
-  };
-  return kVariants[v];
+int variant_bm(int v) { return v == DE_BATCH_TILE32 ? 32 : 64; }
+
+const Kern& tile_kernel(int v) {
+  static const Kern kTile64 = {
+      64, 256, reinterpret_cast<const void*>(&de::k_bt_rot<64, 256, false>),
+      reinterpret_cast<const void*>(&de::k_bt_rot<64, 256, true>)};
+  static const Kern kTile32 = {
+      32, 256, reinterpret_cast<const void*>(&de::k_bt_rot<32, 256, false>),
+      reinterpret_cast<const void*>(&de::k_bt_rot<32, 256, true>)};
+  return v == DE_BATCH_TILE32 ? kTile32 : kTile64;
+}
+
+// The wide variant's kernel for a launch over ntiles tiles whose padded
+// widths are at most dpad_max: 512 threads (two workgroups per CU) when
+// two tiles fit in LDS and there are more tiles than CUs, else 1024.
+const Kern& wide_kernel(int dpad_max, size_t ntiles, int cus) {
+  static const Kern kNarrow = {
+      64, de::kRotBf16ThreadsNarrow,
+      reinterpret_cast<const void*>(
+          &de::k_bt_wide<false, de::kRotBf16ThreadsNarrow>),
+      reinterpret_cast<const void*>(
+          &de::k_bt_wide<true, de::kRotBf16ThreadsNarrow>)};
+  static const Kern kFull = {
+      64, de::kRotBf16Threads,
+      reinterpret_cast<const void*>(&de::k_bt_wide<false, de::kRotBf16Threads>),
+      reinterpret_cast<const void*>(&de::k_bt_wide<true, de::kRotBf16Threads>)};
+  return de::rot_bf16_narrow(dpad_max, (long long)ntiles, cus) ? kNarrow
+                                                               : kFull;
 }
 
 size_t variant_lds(int v, int D) {
   switch (v) {
     case DE_BATCH_TILE64: return de::bt_lds_bytes<64, 256>(dpad_generic(D));
     case DE_BATCH_TILE32: return de::bt_lds_bytes<32, 256>(dpad_generic(D));
-    default:
-      return de::rot_lds_bytes<de::PrecBF16, 64, de::kRotBf16Threads>(
-          dpad_wide(D));
+    default: return de::rot_lds_bytes<de::PrecBF16, 64>(dpad_wide(D));
   }
 }
 
@@ -612,6 +632,7 @@ struct de_batch {
   // one launch per variant in use
   struct Launch {
     int v, ntiles, grid;
+    const Kern* k;
     size_t lds;
     const BTile* tiles;
   };
@@ -676,30 +697,57 @@ std::vector<BTile> tiles_for(const de_batch* b, const std::vector<int>& insts,
   return t;
 }
 
-hipError_t launch_variant(const de_batch* b, int v, bool eval, BatchArgs a,
-                          int ntiles, int grid, size_t lds, const BTile* tiles,
+hipError_t launch_variant(const Kern& k, bool eval, BatchArgs a, int ntiles,
+                          int grid, size_t lds, const BTile* tiles,
                           hipStream_t st) {
   a.tiles = tiles;
   a.ntiles = ntiles;
-  const Variant& var = variant(v);
   void* args[] = {&a};
-  return hipLaunchKernel(eval ? var.eval_fn : var.gen_fn, dim3(grid),
-                         dim3(var.nt), args, lds, st);
+  return hipLaunchKernel(eval ? k.eval_fn : k.gen_fn, dim3(grid), dim3(k.nt),
+                         args, lds, st);
 }
 
 // Workgroups of a launch over ntiles tiles: the generic variants walk the
 // tiles with as many workgroups as fit on the device at once; the wide
 // variant takes one workgroup per tile.
-int persistent_grid(const de_batch* b, int v, size_t lds, int ntiles) {
+int persistent_grid(const de_batch* b, int v, const Kern& k, size_t lds,
+                    int ntiles) {
   if (v == DE_BATCH_WIDE) return std::max(1, ntiles);
   int per_cu = 0;
-  const Variant& var = variant(v);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, var.gen_fn, var.nt,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.gen_fn, k.nt,
                                                    lds) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   const long long cap = (long long)per_cu * b->cus;
   return (int)std::max(1ll, std::min<long long>(cap, ntiles));
+}
+
+// Instances whose variant in vk is v, in launch groups: the wide variant
+// keeps padded widths up to 512 (which may run two workgroups per CU) apart
+// from wider ones; every other variant is one group.
+std::vector<std::vector<int>> launch_groups(const de_batch* b,
+                                            const std::vector<int>& vk,
+                                            int v) {
+  std::vector<int> narrow, rest;
+  for (int k = 0; k < b->ninst; ++k) {
+    if (vk[k] != v) continue;
+    const bool small = v == DE_BATCH_WIDE &&
+                       dpad_wide(b->inst_D[k]) <= de::kRotBf16NarrowMaxDpad;
+    (small ? narrow : rest).push_back(k);
+  }
+  std::vector<std::vector<int>> g;
+  if (!narrow.empty()) g.push_back(narrow);
+  if (!rest.empty()) g.push_back(rest);
+  return g;
+}
+
+// The kernel of a launch of variant v over instances ks and ntiles tiles.
+const Kern& group_kernel(const de_batch* b, int v, const std::vector<int>& ks,
+                         size_t ntiles) {
+  if (v != DE_BATCH_WIDE) return tile_kernel(v);
+  int dmax = 0;
+  for (int k : ks) dmax = std::max(dmax, dpad_wide(b->inst_D[k]));
+  return wide_kernel(dmax, ntiles, b->cus);
 }
 
 // Builds the launches of the current plan (tile lists in the workspace).
@@ -709,29 +757,31 @@ de_status build_launches(de_batch* b, hipStream_t st,
   BTile* dev_tiles = reinterpret_cast<BTile*>(b->work + b->S.L.tiles);
   // host lists stay alive until the copies have completed
   std::vector<std::vector<BTile>> lists;
+  const std::vector<int>& vk = b->plan;
   for (int v = 0; v < DE_BATCH_NVARIANTS; ++v) {
-    std::vector<int> insts;
-    size_t lds = 0;
-    for (int k = 0; k < b->ninst; ++k)
-      if (b->plan[k] == v) {
-        insts.push_back(k);
-        lds = std::max(lds, variant_lds(v, b->inst_D[k]));
-      }
-    if (insts.empty()) continue;
-    lists.push_back(tiles_for(b, insts, variant(v).bm, tile_cost));
-    const std::vector<BTile>& t = lists.back();
-    if (t.empty()) continue;
-    BTile* at = dev_tiles + (size_t)v * b->S.L.max_tiles;
-    de_status rc = FROM_HIP(hipMemcpyAsync(at, t.data(), t.size() * sizeof(BTile),
-                                           hipMemcpyHostToDevice, st));
-    if (rc != DE_OK) return rc;
-    de_batch::Launch l;
-    l.v = v;
-    l.ntiles = (int)t.size();
-    l.lds = lds;
-    l.grid = persistent_grid(b, v, lds, l.ntiles);
-    l.tiles = at;
-    b->launches.push_back(l);
+    // one launch per group (the wide variant may need two block sizes);
+    // their tile lists follow each other in v's region
+    size_t off = 0;
+    for (const std::vector<int>& insts : launch_groups(b, vk, v)) {
+      size_t lds = 0;
+      for (int k : insts) lds = std::max(lds, variant_lds(v, b->inst_D[k]));
+      lists.push_back(tiles_for(b, insts, variant_bm(v), tile_cost));
+      const std::vector<BTile>& t = lists.back();
+      if (t.empty()) continue;
+      BTile* at = dev_tiles + (size_t)v * b->S.L.max_tiles + off;
+      off += t.size();
+      de_status rc = FROM_HIP(hipMemcpyAsync(
+          at, t.data(), t.size() * sizeof(BTile), hipMemcpyHostToDevice, st));
+      if (rc != DE_OK) return rc;
+      de_batch::Launch l;
+      l.v = v;
+      l.k = &group_kernel(b, v, insts, t.size());
+      l.ntiles = (int)t.size();
+      l.lds = lds;
+      l.grid = persistent_grid(b, v, *l.k, lds, l.ntiles);
+      l.tiles = at;
+      b->launches.push_back(l);
+    }
   }
   return FROM_HIP(hipStreamSynchronize(st));
 }
@@ -770,9 +820,9 @@ de_status build_graph(de_batch* b) {
       a.ntiles = l.ntiles;
       void* args[] = {&a};
       hipKernelNodeParams kp{};
-      kp.func = const_cast<void*>(variant(l.v).gen_fn);
+      kp.func = const_cast<void*>(l.k->gen_fn);
       kp.gridDim = dim3(l.grid);
-      kp.blockDim = dim3(variant(l.v).nt);
+      kp.blockDim = dim3(l.k->nt);
       kp.sharedMemBytes = (unsigned)l.lds;
       kp.kernelParams = args;
       kp.extra = nullptr;
@@ -795,7 +845,7 @@ de_status build_graph(de_batch* b) {
 de_status direct_generation(de_batch* b, hipStream_t st) {
   BatchArgs a = base_args(b);
   for (const de_batch::Launch& l : b->launches) {
-    const de_status rc = FROM_HIP(launch_variant(b, l.v, false, a, l.ntiles,
+    const de_status rc = FROM_HIP(launch_variant(*l.k, false, a, l.ntiles,
                                                  l.grid, l.lds, l.tiles, st));
     if (rc != DE_OK) return rc;
   }
@@ -822,7 +872,7 @@ de_status reset_and_best(de_batch* b, hipStream_t st) {
 // generation); the writes go to generation 1's buffers and are discarded.
 de_status time_variant(de_batch* b, int k, int v, hipStream_t st, float* us) {
   const std::vector<double> flat(b->ninst, 0.0);
-  const std::vector<BTile> t = tiles_for(b, {k}, variant(v).bm, flat);
+  const std::vector<BTile> t = tiles_for(b, {k}, variant_bm(v), flat);
   if (t.empty()) {
     *us = 0.f;
     return DE_OK;
@@ -832,10 +882,11 @@ de_status time_variant(de_batch* b, int k, int v, hipStream_t st, float* us) {
   de_status rc = FROM_HIP(hipMemcpyAsync(at, t.data(), t.size() * sizeof(BTile),
                                          hipMemcpyHostToDevice, st));
   if (rc != DE_OK) return rc;
+  const Kern& kern = group_kernel(b, v, {k}, t.size());
   const size_t lds = variant_lds(v, b->inst_D[k]);
-  const int grid = persistent_grid(b, v, lds, (int)t.size());
+  const int grid = persistent_grid(b, v, kern, lds, (int)t.size());
   const BatchArgs a = base_args(b);
-  rc = FROM_HIP(launch_variant(b, v, false, a, (int)t.size(), grid, lds, at, st));
+  rc = FROM_HIP(launch_variant(kern, false, a, (int)t.size(), grid, lds, at, st));
   if (rc != DE_OK) return rc;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return DE_E_DEVICE;
@@ -845,7 +896,7 @@ de_status time_variant(de_batch* b, int k, int v, hipStream_t st, float* us) {
   }
   rc = FROM_HIP(hipEventRecord(e0, st));
   for (int rep = 0; rep < kTuneRepeats && rc == DE_OK; ++rep)
-    rc = FROM_HIP(launch_variant(b, v, false, a, (int)t.size(), grid, lds, at, st));
+    rc = FROM_HIP(launch_variant(kern, false, a, (int)t.size(), grid, lds, at, st));
   if (rc == DE_OK) rc = FROM_HIP(hipEventRecord(e1, st));
   if (rc == DE_OK) rc = FROM_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -870,23 +921,24 @@ de_status eval_default(de_batch* b, hipStream_t st) {
   const BatchArgs a = base_args(b);
   de_status rc = DE_OK;
   for (int v = 0; v < DE_BATCH_NVARIANTS && rc == DE_OK; ++v) {
-    std::vector<int> ks;
-    size_t lds = 0;
-    for (int k = 0; k < b->ninst; ++k)
-      if (eval_v[k] == v) {
-        ks.push_back(k);
-        lds = std::max(lds, variant_lds(v, b->inst_D[k]));
-      }
-    if (ks.empty()) continue;
-    const std::vector<BTile> t = tiles_for(b, ks, variant(v).bm, flat);
-    rc = FROM_HIP(hipMemcpyAsync(scratch, t.data(), t.size() * sizeof(BTile),
-                                 hipMemcpyHostToDevice, st));
-    if (rc == DE_OK)
-      rc = FROM_HIP(launch_variant(b, v, true, a, (int)t.size(),
-                                   persistent_grid(b, v, lds, (int)t.size()),
-                                   lds, scratch, st));
-    // the scratch list is rewritten by the next variant: wait
-    if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
+    for (const std::vector<int>& ks : launch_groups(b, eval_v, v)) {
+      if (rc != DE_OK) break;
+      size_t lds = 0;
+      for (int k : ks) lds = std::max(lds, variant_lds(v, b->inst_D[k]));
+      const std::vector<BTile> t = tiles_for(b, ks, variant_bm(v), flat);
+      if (t.empty()) continue;
+      const Kern& kern = group_kernel(b, v, ks, t.size());
+      rc = FROM_HIP(hipMemcpyAsync(scratch, t.data(),
+                                   t.size() * sizeof(BTile),
+                                   hipMemcpyHostToDevice, st));
+      if (rc == DE_OK)
+        rc = FROM_HIP(launch_variant(kern, true, a, (int)t.size(),
+                                     persistent_grid(b, v, kern, lds,
+                                                     (int)t.size()),
+                                     lds, scratch, st));
+      // the scratch list is rewritten by the next launch: wait
+      if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
+    }
   }
   return rc;
 }
@@ -895,7 +947,7 @@ de_status eval_default(de_batch* b, hipStream_t st) {
 de_status eval_with_launches(de_batch* b, hipStream_t st) {
   const BatchArgs a = base_args(b);
   for (const de_batch::Launch& l : b->launches) {
-    const de_status rc = FROM_HIP(launch_variant(b, l.v, true, a, l.ntiles,
+    const de_status rc = FROM_HIP(launch_variant(*l.k, true, a, l.ntiles,
                                                  l.grid, l.lds, l.tiles, st));
     if (rc != DE_OK) return rc;
   }
@@ -996,13 +1048,19 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
   static std::once_flag attr_once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(attr_once, [] {
-    for (int v = 0; v < DE_BATCH_NVARIANTS && attr_err == hipSuccess; ++v) {
-      attr_err = DE_NOTE(hipFuncSetAttribute(variant(v).gen_fn,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     de::kMaxLdsBytes));
+    // every kernel of every variant (the wide one at both block sizes)
+    const Kern* ks[] = {&tile_kernel(DE_BATCH_TILE64),
+                        &tile_kernel(DE_BATCH_TILE32),
+                        &wide_kernel(de::kRotBf16NarrowMaxDpad, 1, 0),
+                        &wide_kernel(de::kRotBf16NarrowMaxDpad + 1, 1, 0)};
+    for (const Kern* k : ks) {
+      if (attr_err != hipSuccess) break;
+      attr_err = DE_NOTE(hipFuncSetAttribute(
+          k->gen_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+          de::kMaxLdsBytes));
       if (attr_err == hipSuccess)
         attr_err = DE_NOTE(hipFuncSetAttribute(
-            variant(v).eval_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+            k->eval_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
             de::kMaxLdsBytes));
     }
   });
@@ -1098,8 +1156,8 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
     size_t nt = 0;
     for (int r = 0; r < p.nruns; ++r)
       if (b->S.run_inst[r] == k)
-        nt += (size_t)(p.runs[r].NP + variant(b->plan[k]).bm - 1) /
-              variant(b->plan[k]).bm;
+        nt += (size_t)(p.runs[r].NP + variant_bm(b->plan[k]) - 1) /
+              variant_bm(b->plan[k]);
     // untimed (explicit plan): padded MFMA work per tile as the estimate
     const double d = (double)(b->plan[k] == DE_BATCH_WIDE
                                   ? dpad_wide(p.inst[k].D)

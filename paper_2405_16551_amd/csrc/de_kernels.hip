@@ -129,8 +129,13 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
   }
 }
 
+// BF16 tiles of fewer than 1024 threads: two workgroups per CU (four
+// waves per SIMD, 128 registers).
 template <class P, int BM, int NT, bool EVAL, bool JDE>
-__global__ __launch_bounds__(NT) void k_rot(GenArgs a) {
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(
+    (sizeof(typename P::T) == 2 && NT < 1024) ? 4 : 1)))
+void k_rot(GenArgs a) {
   const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
   int run = 0, row0 = 0, nvalid = 0;
   if (EVAL) {
@@ -554,7 +559,7 @@ hipError_t launch_sep_e(const GenArgs& a, hipStream_t s) {
 
 template <class P, int BM, int NT, bool EVAL, bool JDE = false>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
-  const size_t lds = rot_lds_bytes<P, BM, NT, JDE>(a.dpad);
+  const size_t lds = rot_lds_bytes<P, BM, JDE>(a.dpad);
   static bool attr_done = false;
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute(
@@ -574,30 +579,51 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-constexpr int kBf16Threads = kRotBf16Threads;
+// Compute units of the current device (queried once).
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                              dev) == hipSuccess &&
+        n > 0)
+      cus = n;
+    else
+      return 256;
+  }
+  return cus;
+}
 
 template <bool EVAL>
 hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
+  const long long tiles = EVAL ? (a.nrows + 63) / 64
+                               : (long long)a.runs * ((a.NP + 63) / 64);
+  const bool narrow = rot_bf16_narrow(a.dpad, tiles, device_cus());
   if (!EVAL && a.jde) {
     if (prec != kPrecBF16)
       return launch_rot_t<PrecF32, 32, 512, false, true>(a, s);
-    return launch_rot_t<PrecBF16, 64, kBf16Threads, false, true>(a, s);
+    return narrow
+               ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, false,
+                              true>(a, s)
+               : launch_rot_t<PrecBF16, 64, kRotBf16Threads, false, true>(a,
+                                                                          s);
   }
   if (prec != kPrecBF16) return launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
-  return launch_rot_t<PrecBF16, 64, kBf16Threads, EVAL>(a, s);
+  return narrow ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, EVAL>(a, s)
+                : launch_rot_t<PrecBF16, 64, kRotBf16Threads, EVAL>(a, s);
 }
 
 }  // namespace
 
-// LDS bytes of the rotated kernel: BF16 tiles of 64 rows and 1024 threads,
-// FP32 tiles of 32 rows and 512 threads.
+// LDS bytes of the rotated kernel: BF16 tiles of 64 rows, FP32 tiles of 32
+// rows (independent of the number of threads).
 size_t rot_lds_bytes_host(int prec, int dpad, bool jde) {
-  if (jde)
-    return prec == kPrecBF16
-               ? rot_lds_bytes<PrecBF16, 64, kBf16Threads, true>(dpad)
-               : rot_lds_bytes<PrecF32, 32, 512, true>(dpad);
-  return prec == kPrecBF16 ? rot_lds_bytes<PrecBF16, 64, kBf16Threads>(dpad)
-                           : rot_lds_bytes<PrecF32, 32, 512>(dpad);
+  if (prec != kPrecBF16)
+    return jde ? rot_lds_bytes<PrecF32, 32, true>(dpad)
+               : rot_lds_bytes<PrecF32, 32>(dpad);
+  return jde ? rot_lds_bytes<PrecBF16, 64, true>(dpad)
+             : rot_lds_bytes<PrecBF16, 64>(dpad);
 }
 
 bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }

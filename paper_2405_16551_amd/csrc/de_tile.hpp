@@ -66,13 +66,16 @@ struct PrecF32 {
   static constexpr int kPad = 4;
 };
 
-template <class P, int BM, int NT, bool JDE = false>
+// Slots of the per-row objective sums (see rot_tile).
+constexpr int kRotSlots = 16;
+
+template <class P, int BM, bool JDE = false>
 __host__ __device__ constexpr size_t rot_lds_bytes(int dpad) {
   const int tq = (dpad / 4 + 63) / 64;
   return (size_t)BM * (dpad + P::kPad) * sizeof(typename P::T)  // A tile
          + (size_t)BM * tq * 4 * sizeof(unsigned long long)     // planes
          + (size_t)BM * 4 * sizeof(int)                         // donors
-         + (size_t)(NT / 64) * BM * sizeof(float)               // partials
+         + (size_t)kRotSlots * BM * sizeof(float)               // slot sums
          + (JDE ? (size_t)BM * sizeof(Control) : 0);            // F', CR'
 }
 
@@ -117,55 +120,47 @@ __device__ __forceinline__ void osc_accumulate(floatx16& part,
 // 256-coordinate chunks per producer step (rows per step: 8 / this).  One
 // chunk of eight rows measured fastest at D = 1000 (BF16 and FP32 tiles).
 constexpr int kProducerChunks = 1;
-// Rows per producer step of 1024-thread tiles (128 registers per lane).
-constexpr int kRows1024 = 4;
-// Threads of the BF16 rotated tile: 16 waves, four per SIMD, measured
-// faster at D = 1000 than 8 waves with twice the registers each (more
-// waves in flight for the producer's loads and the MFMA loop's L2 reads).
+// Rows per producer step of BF16 tiles (128 registers per lane).
+constexpr int kBf16Rows = 4;
+// Threads of the BF16 rotated tile.  Each wave owns one column block per
+// pass and four producer rows per step, within 128 registers, so four
+// waves fit per SIMD.  The tile has 16 waves (measured faster at D = 1000
+// than 8 waves with twice the registers each), or 8 when two tiles fit in
+// a CU's LDS (padded width up to 512) and there are more tiles than CUs:
+// then each CU holds two and one tile's loads overlap the other's MFMAs.
+// The result does not depend on the choice (row sums add column blocks in
+// a fixed order).
 constexpr int kRotBf16Threads = 1024;
-
-// R fragments of four consecutive K-steps for two column blocks.
-struct BFrags {
-  bf16x8 b0[4], b1[4];
-};
-
-template <int NBW = 2>
-__device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
-                                            const bf16x8* rb1, int kb) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    f.b0[u] = rb0[(size_t)(kb + u) * 64];
-    if constexpr (NBW == 2) f.b1[u] = rb1[(size_t)(kb + u) * 64];
-  }
+constexpr int kRotBf16ThreadsNarrow = 512;
+constexpr int kRotBf16NarrowMaxDpad = 512;
+__host__ __device__ constexpr bool rot_bf16_narrow(int dpad, long long tiles,
+                                                   int cus) {
+  return dpad <= kRotBf16NarrowMaxDpad && tiles > cus;
 }
 
-// Scheduling pattern for one K-step: its LDS reads (next A fragments) and
-// L2 loads (R fragments of a later step) are placed between its MFMAs
-// instead of in one burst, so the matrix unit keeps busy while they go out.
-template <int MB, int NBW = 2>
+// R fragments of four consecutive K-steps of one column block.
+struct BFrags {
+  bf16x8 b0[4];
+};
+
+__device__ __forceinline__ void load_bfrags(BFrags& f, const bf16x8* rb0,
+                                            int kb) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) f.b0[u] = rb0[(size_t)(kb + u) * 64];
+}
+
+// Scheduling pattern for one K-step: per row block one MFMA and its next A
+// read (LDS), then the step's R load (L2), so the matrix unit keeps busy
+// while the reads go out instead of waiting behind one burst.
+template <int MB>
 __device__ __forceinline__ void interleave_step() {
-  if constexpr (NBW == 2) {
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
-    if constexpr (MB == 2) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-    }
-  } else {
-    // one column block: per row block one MFMA and its next A read, then
-    // the step's R load
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+  if constexpr (MB == 2) {
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    if constexpr (MB == 2) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
   }
+  __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -195,9 +190,9 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   constexpr int MB = BM / 32;
   constexpr int kRotThreads = NT;
   constexpr int kRotWaves = NT / 64;
-  // 1024-thread tiles (four waves per SIMD, 128 registers each): one
-  // column block per wave and pass, four producer rows per step
-  constexpr int NBW = NT >= 1024 ? 1 : 2;
+  // BF16 tiles: one column block per wave and pass, four producer rows per
+  // step (128 registers); FP32 tiles: two column blocks, eight rows
+  constexpr int NBW = sizeof(T) == 2 ? 1 : 2;
   static_assert(MB == 1 || (MB == 2 && sizeof(T) == 2), "tile shape");
   static_assert(NBW == 2 || sizeof(T) == 2, "FP32 tiles use two blocks");
   extern __shared__ __align__(16) char smem[];
@@ -210,7 +205,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   int* donors = reinterpret_cast<int*>(planes + (size_t)BM * tq * 4);
   float* fpart = reinterpret_cast<float*>(donors + BM * 4);
   // jDE: the F' and CR' of every row of the tile
-  Control* ctl = reinterpret_cast<Control*>(fpart + kRotWaves * BM);
+  Control* ctl = reinterpret_cast<Control*>(fpart + kRotSlots * BM);
 
   const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
   const uint32_t rng_run = a.run_base + (uint32_t)run;
@@ -255,7 +250,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     // past the wave's last go to its last row (values unused), so no load
     // sits behind a per-lane branch.
     constexpr int CG = kProducerChunks;
-    constexpr int RB = (NT >= 1024 ? kRows1024 : 8) / CG;
+    constexpr int RB = (sizeof(T) == 2 ? kBf16Rows : 8) / CG;
     const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
     const int dlast = ((a.D + 3) / 4 - 1) * 4;
     for (int t0 = 0; t0 < tq; t0 += CG) {
@@ -366,29 +361,42 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   // Wave w of every workgroup streams the same R fragments at about the same
   // time, so concurrent requests from the CUs of an XCD share L2 lines.
   const int nblk = dpad / 32;
-  floatx16 part0 = {}, part1 = {};
-  for (int nb0 = wave * NBW; nb0 < nblk; nb0 += kRotWaves * NBW) {
-    floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
+  // Row sums of the objective go to kRotSlots slots: slot s adds column
+  // blocks s, s + 16, s + 32, ... in increasing order, so the result does
+  // not depend on how blocks are dealt to waves (the number of threads).
+  // A wave's blocks fall into SPW slots, its pass p into sacc[p % SPW].
+  constexpr int SPW = kRotSlots / (kRotWaves * NBW) > 1
+                          ? kRotSlots / (kRotWaves * NBW)
+                          : 1;
+  static_assert(kRotSlots % (kRotWaves * NBW) == 0 ||
+                    (kRotWaves * NBW) % kRotSlots == 0,
+                "slots and waves");
+  float sacc[SPW];
+#pragma unroll
+  for (int q = 0; q < SPW; ++q) sacc[q] = 0.f;
+  int pass = 0;
+  for (int nb0 = wave * NBW; nb0 < nblk;
+       nb0 += kRotWaves * NBW, ++pass) {
+    floatx16 c00 = {}, c01 = {}, c10 = {};
     if constexpr (sizeof(T) == 2) {
       // R as [nblk][dpad/16][64 lanes][8]: one 16-byte load per lane per
       // block and K-step; dpad / 16 is a multiple of 4.
       const bf16x8* rop = reinterpret_cast<const bf16x8*>(a.rop);
       const int kbn = dpad / 16;
       const bf16x8* rb0 = rop + ((size_t)nb0 * kbn) * 64 + lane;
-      const bf16x8* rb1 = rb0 + (size_t)kbn * 64;
       const T* ar = At + (size_t)(lane % 32) * stride + 8 * (lane / 32);
       // Software pipeline at K-step granularity: the A fragments of step
       // k + 1 are read from LDS while step k's MFMAs run (two slots), and
       // the R fragments of the next four-step group are loaded from L2 one
-      // pair per step into the other of two register sets.  Each step's
-      // reads are interleaved with its four MFMAs.  dpad / 16 is a multiple
-      // of 8.
+      // per step into the other of two register sets.  Each step's reads
+      // are interleaved with its MFMAs (one per row block).  dpad / 16 is a
+      // multiple of 8.
       const T* ar1 = ar + (size_t)32 * stride;
       bf16x8 a0s[2], a1s[2];
       BFrags fa, fb;
       a0s[0] = *reinterpret_cast<const bf16x8*>(ar);
       if constexpr (MB == 2) a1s[0] = *reinterpret_cast<const bf16x8*>(ar1);
-      load_bfrags<NBW>(fa, rb0, rb1, 0);
+      load_bfrags(fa, rb0, 0);
       for (int kb = 0; kb < kbn; kb += 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -401,28 +409,17 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
           }
           if (u < 4) {
             fb.b0[u] = rb0[(size_t)(kb + 4 + u) * 64];
-            if constexpr (NBW == 2) fb.b1[u] = rb1[(size_t)(kb + 4 + u) * 64];
           } else if (kb + 8 < kbn) {
             fa.b0[u - 4] = rb0[(size_t)(kb + 8 + u - 4) * 64];
-            if constexpr (NBW == 2)
-              fa.b1[u - 4] = rb1[(size_t)(kb + 8 + u - 4) * 64];
           }
           const bf16x8 b0 = u < 4 ? fa.b0[u & 3] : fb.b0[u & 3];
           c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b0, c00, 0, 0,
                                                         0);
-          if constexpr (NBW == 2) {
-            const bf16x8 b1 = u < 4 ? fa.b1[u & 3] : fb.b1[u & 3];
-            c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0s[cur], b1, c01, 0,
-                                                          0, 0);
-            if constexpr (MB == 2)
-              c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b1, c11,
-                                                            0, 0, 0);
-          }
           if constexpr (MB == 2) {
             c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1s[cur], b0, c10, 0,
                                                           0, 0);
           }
-          interleave_step<MB, NBW>();
+          interleave_step<MB>();
         }
       }
     } else {
@@ -448,39 +445,61 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
         f32_step(ar, k8 + 1, q01, q11, c00, c01);
       }
     }
+    // The objective of each 32-column block, summed per row and written to
+    // the block's LDS slot; rows then add the slots in block order, so the
+    // result does not depend on how blocks are dealt to waves (the number
+    // of threads).  32x32 accumulator layout: register r of lane l holds
+    // row 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.
+    // Each lane has 32 values (BF16: rows of row blocks 0 and 1; FP32: one
+    // row block, column blocks nb0 and nb0 + 1); a reduce-scatter butterfly
+    // over the 32 lanes of each half-wave leaves lane l with the total of
+    // value l % 32 (31 exchanges instead of 5 per value).
     constexpr bool kFastSin = sizeof(T) == 2;
-    osc_accumulate<kFastSin>(part0, c00);
-    if constexpr (NBW == 2) osc_accumulate<kFastSin>(part0, c01);
-    if constexpr (MB == 2) {
-      osc_accumulate<kFastSin>(part1, c10);
-      if constexpr (NBW == 2) osc_accumulate<kFastSin>(part1, c11);
-    }
-  }
-  // 32x32 accumulator layout: register r of lane l holds row
-  // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the block.  Each lane
-  // has 32 per-row partial sums (value v = 16 m + r); a reduce-scatter
-  // butterfly over the 32 lanes of each half-wave leaves lane l with the
-  // total of value v = l % 32 (31 exchanges instead of 5 per value).
-  {
-    float v[32];
+    floatx16& lo = c00;
+    floatx16& hi = MB == 2 ? c10 : c01;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      v[r] = part0[r];
-      v[16 + r] = MB == 2 ? part1[r] : 0.f;
+      lo[r] = osc_term<kFastSin>(lo[r]);
+      hi[r] = osc_term<kFastSin>(hi[r]);
+    }
+    {  // first exchange: values 0-15 keep lo or hi, the other half goes over
+      const bool upper = (lane & 16) != 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const float send = upper ? lo[k] : hi[k];
+        const float keep = upper ? hi[k] : lo[k];
+        lo[k] = keep + __shfl_xor(send, 16, 64);
+      }
     }
 #pragma unroll
-    for (int m = 16, n = 32; m >= 1; m >>= 1, n >>= 1) {
+    for (int m = 8, n = 16; m >= 1; m >>= 1, n >>= 1) {
       const bool upper = (lane & m) != 0;
 #pragma unroll
       for (int k = 0; k < n / 2; ++k) {
-        const float send = upper ? v[k] : v[k + n / 2];
-        const float keep = upper ? v[k + n / 2] : v[k];
-        v[k] = keep + __shfl_xor(send, m, 64);
+        const float send = upper ? lo[k] : lo[k + n / 2];
+        const float keep = upper ? lo[k + n / 2] : lo[k];
+        lo[k] = keep + __shfl_xor(send, m, 64);
       }
     }
-    const int idx = lane % 32, mb = idx / 16, r = idx % 16;
-    const int row = mb * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-    if (mb < MB) fpart[wave * BM + row] = v[0];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q)
+      if (pass % SPW == q) sacc[q] += lo[0];
+  }
+  // lane l holds value l % 32: BF16 row (l % 32 / 16) * 32 + rin of the
+  // wave's blocks; FP32 row rin of block nb0 + (l % 32) / 16
+  {
+    const int idx = lane % 32, hb = idx / 16, r = idx % 16;
+    const int rin = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+      const int b0 = wave * NBW + q * kRotWaves * NBW;  // first block of q
+      if constexpr (MB == 2) {
+        if (b0 < kRotSlots) fpart[(size_t)b0 * BM + hb * 32 + rin] = sacc[q];
+      } else {
+        if (b0 + hb < kRotSlots)
+          fpart[(size_t)(b0 + hb) * BM + rin] = sacc[q];
+      }
+    }
   }
   __syncthreads();
 
@@ -488,7 +507,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   for (int rl = wave; rl < nvalid; rl += kRotWaves) {
     float f = 0.f;
 #pragma unroll
-    for (int w = 0; w < kRotWaves; ++w) f += fpart[w * BM + rl];
+    for (int sl = 0; sl < kRotSlots; ++sl) f += fpart[sl * BM + rl];
     const int i = row0 + rl;
     if (EVAL) {
       if (lane == 0) a.fit_next[i] = f;

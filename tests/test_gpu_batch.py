@@ -99,11 +99,12 @@ def test_batch_generation_matches_oracle(variant):
 def test_wide_variant_equals_per_problem_handle():
     # the wide variant runs the per-problem BF16 tile with the run's own
     # arguments: run r of a batch equals run r of a de.h handle bit for bit
-    # (D = 200 pads to 256 in both)
-    specs = [(64, 200, 0.5, 0.9), (100, 200, 0.5, 0.9)]
+    # (D = 200 pads to 256 in both: 512-thread tiles, two per CU; D = 600
+    # pads to 640: 1024-thread tiles; one plan, two wide launches)
+    specs = [(64, 200, 0.5, 0.9), (100, 200, 0.5, 0.9), (40, 600, 0.6, 0.8)]
     from paper_2405_16551_amd.de import DE_BATCH_WIDE
-    b, inst = make_batch(specs, plan={200: DE_BATCH_WIDE}, graph_gens=4)
-    o, R = inst[200]
+    b, inst = make_batch(specs, plan={200: DE_BATCH_WIDE, 600: DE_BATCH_WIDE},
+                         graph_gens=4)
     single = []
     for r, (NP, D, F, CR) in enumerate(specs):
         de, _, _ = make_de(runs=r + 1, NP=NP, D=D, F=F, CR=CR, seed=1,
@@ -112,6 +113,27 @@ def test_wide_variant_equals_per_problem_handle():
     b.generation(30)
     for r, de in enumerate(single):
         de.generation(30)
+        np.testing.assert_array_equal(host(b.population(r)),
+                                      host(de.population())[r])
+        np.testing.assert_array_equal(host(b.fitness(r)),
+                                      host(de.fitness())[r])
+        de.close()
+    b.close()
+
+
+def test_wide_tile_threads_do_not_change_results():
+    # 300 runs of D = 200: more wide tiles than compute units, so the batch
+    # runs 512-thread tiles (two per CU); handles of at most 201 runs use
+    # 1024-thread tiles.  Row sums add column blocks in a fixed order, so
+    # the values agree bit for bit.
+    specs = [(64, 200, 0.5, 0.9)] * 300
+    from paper_2405_16551_amd.de import DE_BATCH_WIDE
+    b, inst = make_batch(specs, plan={200: DE_BATCH_WIDE}, graph_gens=4)
+    b.generation(12)
+    for r in (0, 17, 200):
+        de, _, _ = make_de(runs=r + 1, NP=64, D=200, F=0.5, CR=0.9, seed=1,
+                           kind="rot_osc", gemm_prec="bf16")
+        de.generation(12)
         np.testing.assert_array_equal(host(b.population(r)),
                                       host(de.population())[r])
         np.testing.assert_array_equal(host(b.fitness(r)),

@@ -135,6 +135,25 @@ def test_one_generation_bf16_gemm():
     assert ties <= n // 10
 
 
+def test_one_generation_bf16_two_tiles_per_cu():
+    # more 64-row tiles than compute units at a padded width of 256: the
+    # BF16 tile runs with 512 threads, two workgroups per CU
+    runs, NP, D = 2, 8256, 256
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=5, kind="rot_osc",
+                       gemm_prec="bf16")
+    de.generation(2)
+    g = de.gen
+    pop32 = host(de.population()).copy()
+    fit_prev = host(de.fitness()).copy()
+    de.generation(1)
+    n, ties = compare_generation(host(de.population()), host(de.fitness()),
+                                 pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
+                                 kind=oracle.OBJ_ROT_OSC, o=o, R=R,
+                                 f_rtol=bf16_rtol(D))
+    assert n == runs * NP
+    assert ties <= n // 10
+
+
 # ---------------------------------------------------------------------------
 # Objective evaluation through the generation kernels' arithmetic.
 
