@@ -468,9 +468,9 @@ def main():
                     help="run one 256 MiB device copy first (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the DE step is single-GPU in "
-              "this build (independent runs would shard across GPUs with no "
-              "exchange); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the DE step runs on one GPU "
+              "(independent runs would shard across GPUs with no exchange); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

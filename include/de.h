@@ -53,7 +53,7 @@ typedef enum de_status {
   DE_E_NOMEM = 2,       /* host allocation of the handle failed            */
   DE_E_DEVICE = 3,      /* a HIP call or a kernel failed                   */
   DE_E_STATE = 4,       /* NULL / destroyed handle, or wrong call order    */
-  DE_E_UNSUPPORTED = 5  /* valid, but beyond what this build implements    */
+  DE_E_UNSUPPORTED = 5  /* valid, but beyond what the library implements  */
 } de_status;
 
 /* Objective kinds (Section 7.3.1 transform; minimisation, optimum f = 0 at
@@ -141,7 +141,7 @@ DE_API const char* de_strerror(de_status status);
 
 /* Bytes of device workspace needed for (params, objective).  Pure host
  * computation.  DE_E_INVAL on bad arguments, DE_E_UNSUPPORTED for sizes the
- * kernels of this build do not cover.                                      */
+ * library's kernels do not cover.                                         */
 DE_API de_status de_workspace_bytes(const de_params* params,
                              const de_objective* objective, size_t* bytes);
 

@@ -245,7 +245,7 @@ DE_API const char* de_strerror(de_status status) {
     case DE_E_NOMEM: return "host allocation failed";
     case DE_E_DEVICE: return "HIP runtime or kernel failure";
     case DE_E_STATE: return "invalid or destroyed handle, or wrong call order";
-    case DE_E_UNSUPPORTED: return "size not supported by this build";
+    case DE_E_UNSUPPORTED: return "size not supported by the library";
   }
   return "unknown status";
 }

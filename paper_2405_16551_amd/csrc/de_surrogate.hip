@@ -466,7 +466,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_sur_select(SurArgs a) {
   }
 }
 
-// Generation 0 into the archive (round 0): rows and their targets.
+// Generation 0 into the archive (its first fill): rows and their targets.
 __global__ __launch_bounds__(256) void k_archive_init(SurArgs a) {
   const int nq = (a.D + 3) / 4;
   const size_t total = (size_t)a.runs * a.NP * nq;
