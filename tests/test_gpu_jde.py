@@ -44,6 +44,8 @@ def make_jde(**kw):
     ("sphere", "fp32", 3, 50, 37), ("sphere", "fp32", 2, 4, 1),
     ("sphere", "fp32", 3, 45, 600), ("sphere", "fp32", 2, 30, 1500),
     ("rot_osc", "fp32", 2, 70, 100), ("rot_osc", "bf16", 2, 130, 100),
+    # more tiles than compute units at padded width 256: 512-thread tiles
+    ("rot_osc", "bf16", 2, 8256, 200),
 ])
 def test_jde_generation_matches_oracle(kind, prec, runs, NP, D):
     de, o, R = make_jde(runs=runs, NP=NP, D=D, F=0.5, CR=0.9, seed=3,
