@@ -275,3 +275,15 @@ def test_surrogate_calls_on_missing_handles():
     assert d._lib.de_sur_get_model(None, None, f, f, f, None) == d.DE_E_STATE
     assert d._lib.de_sur_train(None, 1, None) == d.DE_E_STATE
     assert d._lib.de_sur_destroy(None) == d.DE_E_STATE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the step runs on one GPU; asking for more exits with a message
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
