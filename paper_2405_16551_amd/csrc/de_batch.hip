@@ -1045,26 +1045,17 @@ DE_API de_status de_batch_create(const de_batch_params* params, float* pop0,
       DE_NOTE(hipGetDeviceProperties(&prop, dev)) != hipSuccess)
     return fail(DE_E_DEVICE);
   b->cus = prop.multiProcessorCount;
-  static std::once_flag attr_once;
-  static hipError_t attr_err = hipSuccess;
-  std::call_once(attr_once, [] {
+  {
     // every kernel of every variant (the wide one at both block sizes)
     const Kern* ks[] = {&tile_kernel(DE_BATCH_TILE64),
                         &tile_kernel(DE_BATCH_TILE32),
                         &wide_kernel(de::kRotBf16NarrowMaxDpad, 1, 0),
                         &wide_kernel(de::kRotBf16NarrowMaxDpad + 1, 1, 0)};
-    for (const Kern* k : ks) {
-      if (attr_err != hipSuccess) break;
-      attr_err = DE_NOTE(hipFuncSetAttribute(
-          k->gen_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-          de::kMaxLdsBytes));
-      if (attr_err == hipSuccess)
-        attr_err = DE_NOTE(hipFuncSetAttribute(
-            k->eval_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-            de::kMaxLdsBytes));
-    }
-  });
-  if (attr_err != hipSuccess) return fail(DE_E_DEVICE);
+    for (const Kern* k : ks)
+      if (DE_NOTE(de::set_max_dynamic_lds(k->gen_fn)) != hipSuccess ||
+          DE_NOTE(de::set_max_dynamic_lds(k->eval_fn)) != hipSuccess)
+        return fail(DE_E_DEVICE);
+  }
 
   // tables and instance data
   const BLayout& L = b->S.L;

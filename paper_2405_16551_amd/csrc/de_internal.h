@@ -43,6 +43,10 @@ struct GenArgs {
 hipError_t note_hip(hipError_t e, const char* file, int line);
 #define DE_NOTE(expr) ::de::note_hip((expr), __FILE__, __LINE__)
 
+// Allows kernel fn the dynamic LDS that its static LDS leaves free of the
+// CU's 160 KB, on the current device (once per kernel and device).
+hipError_t set_max_dynamic_lds(const void* fn);
+
 size_t rot_lds_bytes_host(int prec, int dpad, bool jde = false);
 bool sep_supported(int D);
 

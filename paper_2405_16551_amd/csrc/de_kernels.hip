@@ -23,6 +23,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
+#include <set>
+#include <utility>
 
 #include "de_device.hpp"
 #include "de_internal.h"
@@ -560,14 +563,9 @@ hipError_t launch_sep_e(const GenArgs& a, hipStream_t s) {
 template <class P, int BM, int NT, bool EVAL, bool JDE = false>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   const size_t lds = rot_lds_bytes<P, BM, JDE>(a.dpad);
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL, JDE>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
-    if (e != hipSuccess) return e;
-    attr_done = true;
-  }
+  const hipError_t e = set_max_dynamic_lds(
+      reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL, JDE>));
+  if (e != hipSuccess) return e;
   int blocks;
   if (EVAL) {
     blocks = (a.nrows + BM - 1) / BM;
@@ -627,6 +625,23 @@ size_t rot_lds_bytes_host(int prec, int dpad, bool jde) {
 }
 
 bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
+
+hipError_t set_max_dynamic_lds(const void* fn) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count({fn, dev})) return hipSuccess;
+  hipFuncAttributes fa{};
+  e = hipFuncGetAttributes(&fa, fn);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kMaxLdsBytes - (int)fa.sharedSizeBytes);
+  if (e == hipSuccess) done.insert({fn, dev});
+  return e;
+}
 
 hipError_t note_hip(hipError_t e, const char* file, int line) {
   if (e != hipSuccess) {

@@ -1067,24 +1067,15 @@ SurArgs args_of(const de_sur* s) {
 }
 
 de_status set_lds_attributes() {
-  static std::once_flag once;
-  static hipError_t err = hipSuccess;
-  std::call_once(once, [] {
-    const void* fns[] = {reinterpret_cast<const void*>(&de::k_comp_eval),
-                         reinterpret_cast<const void*>(&de::k_sur_select),
-                         reinterpret_cast<const void*>(&de::k_mlp_infer),
-                         reinterpret_cast<const void*>(&de::k_train_fwd)};
-    // dynamic LDS may use what the kernel's static LDS leaves free
-    for (const void* f : fns) {
-      hipFuncAttributes fa{};
-      if (err == hipSuccess) err = hipFuncGetAttributes(&fa, f);
-      if (err == hipSuccess)
-        err = hipFuncSetAttribute(
-            f, hipFuncAttributeMaxDynamicSharedMemorySize,
-            de::kMaxLdsBytes - (int)fa.sharedSizeBytes);
-    }
-  });
-  return FROM_HIP(err);
+  const void* fns[] = {reinterpret_cast<const void*>(&de::k_comp_eval),
+                       reinterpret_cast<const void*>(&de::k_sur_select),
+                       reinterpret_cast<const void*>(&de::k_mlp_infer),
+                       reinterpret_cast<const void*>(&de::k_train_fwd)};
+  for (const void* f : fns) {
+    const de_status rc = FROM_HIP(de::set_max_dynamic_lds(f));
+    if (rc != DE_OK) return rc;
+  }
+  return DE_OK;
 }
 
 de_status prep_model(de_sur* s, hipStream_t st) {
