@@ -8,10 +8,12 @@ step = one synchronous generation of all 16 x 1024 trials (draws, mutation,
 crossover, fitness, selection, write of the next generation).
 
 Prints one JSON line.  value = trial evaluations per second over the timed
-steps (inputs resident in HBM; the timed steps are one library call of K
-generations).  Also reported: generations per second, the roofline
-position of the generation kernel (HIP events around the K launches,
-algorithmic FLOPs 2 D^2 per trial), a separable companion workload
+steps (inputs resident in HBM; the timed steps are five back-to-back
+library calls of about K/5 generations each).  Also reported: generations
+per second, the median and spread of the five segments, the handle's
+initialisation time, the roofline position of the generation kernel (HIP
+events around the K launches, algorithmic FLOPs 2 D^2 per trial), a
+separable companion workload
 (shifted sphere, same sizes; HBM roofline), wall time to the 1e-8 target
 on the small sphere workload (Section 7.3.4 early stopping), wall time to
 the FP64 oracle's median final best on the rotated D = 100 workload (64
@@ -114,27 +116,37 @@ def time_workload(name, steps, warmup, seed=1):
 
     w = WORKLOADS[name]
     o, R = instances.make_instance(w["kind"], w["D"], 1)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter()
     de = DifferentialEvolution(runs=w["runs"], NP=w["NP"], D=w["D"], F=0.5,
                                CR=0.9, seed=seed, kind=w["kind"], o=o, R=R,
                                gemm_prec=w["gemm_prec"],
                                jde=w.get("jde"))
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t_init) * 1e3
     stream = de.stream
     de.generation(warmup)
     torch.cuda.synchronize()
     acc0, _ = de.stats()
-    # the K steps are one library call (K launches back to back on the
-    # library's stream); events on that stream bracket them, so the average
-    # launch duration includes the gaps between consecutive launches
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
+    # the K steps are five library calls of about K/5 generations each
+    # (launches back to back on the library's stream); events on that
+    # stream bracket every call, so the average launch duration includes
+    # the gaps between consecutive launches, and the five segments give a
+    # median and a spread
+    nseg = 5 if steps >= 5 else 1
+    cuts = [steps * k // nseg for k in range(nseg + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record(stream)
-    de.generation(steps)
-    end.record(stream)
+    ev[0].record(stream)
+    for k in range(nseg):
+        de.generation(cuts[k + 1] - cuts[k])
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = start.elapsed_time(end) / steps
+    kern_ms = ev[0].elapsed_time(ev[nseg]) / steps
+    seg_ms = sorted(ev[k].elapsed_time(ev[k + 1]) / (cuts[k + 1] - cuts[k])
+                    for k in range(nseg))
     trials = w["runs"] * w["NP"]
     acc1, best = de.stats()
     accept_rate = (sum(acc1) - sum(acc0)) / float(trials * steps)
@@ -153,7 +165,11 @@ def time_workload(name, steps, warmup, seed=1):
         bound = "hbm"
     de.close()
     return dict(wall_s=wall, ms_per_step=wall / steps * 1e3,
-                kernel_ms=kern_ms, evals_per_s=trials * steps / wall,
+                kernel_ms=kern_ms, init_ms=init_ms,
+                segments=dict(n=nseg, median_ms_per_step=round(
+                    seg_ms[nseg // 2], 5), min_ms_per_step=round(seg_ms[0], 5),
+                    max_ms_per_step=round(seg_ms[-1], 5)),
+                evals_per_s=trials * steps / wall,
                 gens_per_s=steps / wall, accept_rate=round(accept_rate, 4),
                 roofline=dict(bound=bound, achieved=round(achieved, 3),
                               peak=peak, unit=unit,
@@ -519,6 +535,8 @@ def main():
                    "objective": w["kind"], "gemm": w["gemm_prec"]},
         "gens_per_s": round(main_res["gens_per_s"], 2),
         "kernel_ms_per_step": round(main_res["kernel_ms"], 5),
+        "segments": main_res["segments"],
+        "init_ms": round(main_res["init_ms"], 3),
         "roofline": main_res["roofline"],
         "accept_rate": main_res["accept_rate"],
         "best_vs_fp64": main_res["best_vs_fp64"],
