@@ -6,6 +6,7 @@
 // through de_internal.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -216,7 +217,31 @@ float f_of_key(unsigned long long key) {
   return f;
 }
 
+// Generations per launch of the resident separable form.
+constexpr int64_t kResidentChunk = 1024;
+
 de_status run_generations(de_state* s, int64_t n, hipStream_t st) {
+  // small separable problems: several generations per launch, each run's
+  // population resident in LDS (results equal the per-generation kernel's)
+  if (n >= 2 && s->kind == de::kObjSphere && !s->jde &&
+      de::sep_resident_fits(s->p.NP, s->ldx, s->p.D)) {
+    while (n > 0) {
+      const int m = (int)std::min<int64_t>(n, kResidentChunk);
+      GenArgs a = base_args(s);
+      const int b = (int)(s->gen & 1);
+      a.pop_cur = s->pop[b];
+      a.fit_cur = s->fit[b];
+      a.pop_next = s->pop[b ^ 1];
+      a.fit_next = s->fit[b ^ 1];
+      const int fb = (int)((s->gen + m) & 1);
+      const de_status rc = FROM_HIP(
+          de::launch_sep_resident(a, m, s->pop[fb], s->fit[fb], st));
+      if (rc != DE_OK) return rc;
+      s->gen += m;
+      n -= m;
+    }
+    return DE_OK;
+  }
   for (int64_t k = 0; k < n; ++k) {
     GenArgs a = base_args(s);
     const int b = (int)(s->gen & 1);

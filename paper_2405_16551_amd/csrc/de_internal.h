@@ -50,6 +50,15 @@ hipError_t set_max_dynamic_lds(const void* fn);
 size_t rot_lds_bytes_host(int prec, int dpad, bool jde = false);
 bool sep_supported(int D);
 
+// Resident form of the separable step (one workgroup per run, population in
+// LDS for several generations): for rows of at most 256 coordinates whose
+// two buffers fit in kSepResidentMaxLds bytes.
+constexpr size_t kSepResidentMaxLds = 64 * 1024;
+size_t sep_resident_lds_bytes(int NP, int ldx, int D);
+bool sep_resident_fits(int NP, int ldx, int D);
+hipError_t launch_sep_resident(const GenArgs& a, int n_gens, float* pop_final,
+                               float* fit_final, hipStream_t s);
+
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,
                              hipStream_t s);
 hipError_t launch_eval(const GenArgs& a, int kind, int prec, hipStream_t s);

@@ -369,6 +369,108 @@ __global__ __launch_bounds__(256) void k_debug_draws(GenArgs a, int* idx4,
 // Launchers.
 
 // ---------------------------------------------------------------------------
+// Separable objective, resident form for small problems (rows of at most 256
+// coordinates, a run's two population buffers within the LDS limit): one
+// workgroup per run keeps the population, fitness and shift in LDS for
+// n_gens generations.  Each generation is computed exactly as k_sep<LPI, 1>
+// computes it (same lanes per individual, draws, operations and summation
+// order), so the result equals n_gens launches of k_sep bit for bit; what
+// is saved is the launch and the global round trip per generation.  The
+// final generation goes to pop_final / fit_final, and every row is marked
+// changed (the other global buffer is stale).
+template <int LPI>
+__global__ __launch_bounds__(1024) void k_sep_resident(GenArgs a, int n_gens,
+                                                       float* pop_final,
+                                                       float* fit_final) {
+  extern __shared__ __align__(16) float rs[];
+  const int run = (int)blockIdx.x;
+  const int NP = a.NP, ldx = a.ldx, D = a.D;
+  const int dq = (D + 3) / 4 * 4;  // shift floats used
+  // P0, P1 [NP][ldx] and the shift (16-byte aligned: ldx % 4 == 0), then
+  // F0, F1 [NP]
+  float* P0 = rs;
+  float* P1 = P0 + (size_t)NP * ldx;
+  float* so = P1 + (size_t)NP * ldx;
+  float* F0 = so + dq;
+  float* F1 = F0 + NP;
+  const size_t row0 = (size_t)run * NP;
+  {
+    const float4* src =
+        reinterpret_cast<const float4*>(a.pop_cur + row0 * ldx);
+    const int n4 = NP * ldx / 4;
+    for (int t = (int)threadIdx.x; t < n4; t += (int)blockDim.x) {
+      const float4 v = src[t];
+      reinterpret_cast<float4*>(P0)[t] = v;
+      reinterpret_cast<float4*>(P1)[t] = v;  // padding alike in both
+    }
+    for (int t = (int)threadIdx.x; t < NP; t += (int)blockDim.x)
+      F0[t] = a.fit_cur[row0 + t];
+    for (int t = (int)threadIdx.x; t < dq; t += (int)blockDim.x)
+      so[t] = a.o[t];
+  }
+  __syncthreads();
+  const int groups = (int)blockDim.x / LPI;
+  const int slot = (int)threadIdx.x / LPI, ln = (int)threadIdx.x % LPI;
+  const int dlast = ((D + 3) / 4 - 1) * 4;
+  const int jl = min(4 * ln, dlast), j0 = 4 * ln;
+  const float4 ov = ld4(so + jl);
+  for (int gi = 0; gi < n_gens; ++gi) {
+    const uint32_t gen = a.gen + (uint32_t)gi;
+    const float* Pc = (gi & 1) ? P1 : P0;
+    float* Pn = (gi & 1) ? P0 : P1;
+    const float* Fc = (gi & 1) ? F1 : F0;
+    float* Fn = (gi & 1) ? F0 : F1;
+    for (int i = slot; i - slot < NP; i += groups) {
+      if (i >= NP) continue;  // whole LPI-groups, whose shuffles stay inside
+      const Donors d = pick_donors((uint32_t)run, gen, i, NP, D, a.key_lo,
+                                   a.key_hi);
+      const float4 xv = ld4(Pc + (size_t)i * ldx + jl);
+      const float4 v1 = ld4(Pc + (size_t)d.r1 * ldx + jl);
+      const float4 v2 = ld4(Pc + (size_t)d.r2 * ldx + jl);
+      const float4 v3 = ld4(Pc + (size_t)d.r3 * ldx + jl);
+      const Words4 w = draw_block(kTagXover, (uint32_t)run, gen, (uint32_t)i,
+                                  (uint32_t)ln, a.key_lo, a.key_hi);
+      float4 uv = xv;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bool tk = (j0 + b < D) &&
+                        take_mutant(w.w[b], j0 + b, d.jrand, a.cr_threshold);
+        const float mv = mutant_coord(get(v1, b), get(v2, b), get(v3, b), a.F,
+                                      a.lo, a.hi);
+        set(uv, b, tk ? mv : get(xv, b));
+      }
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const float y = get(uv, b) - get(ov, b);
+        acc = (j0 + b < D) ? fmaf(y, y, acc) : acc;
+      }
+      const float f = group_sum<LPI>(acc);
+      const float fx = Fc[i];
+      const bool accept = f < fx;
+      if (j0 < D) st4(Pn + (size_t)i * ldx + j0, accept ? uv : xv);
+      if (ln == 0) {
+        Fn[i] = accept ? f : fx;
+        if (accept) record_accept_at(a, run, i, f, gen);
+      }
+    }
+    __syncthreads();
+  }
+  const float* Pf = (n_gens & 1) ? P1 : P0;
+  const float* Ff = (n_gens & 1) ? F1 : F0;
+  {
+    float4* dst = reinterpret_cast<float4*>(pop_final + row0 * ldx);
+    const int n4 = NP * ldx / 4;
+    for (int t = (int)threadIdx.x; t < n4; t += (int)blockDim.x)
+      dst[t] = reinterpret_cast<const float4*>(Pf)[t];
+    for (int t = (int)threadIdx.x; t < NP; t += (int)blockDim.x) {
+      fit_final[row0 + t] = Ff[t];
+      a.changed[row0 + t] = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Separable objective, one wave per row, rows of more than 256 coordinates
 // (ITER float4 per lane).  The work per row is mostly VALU, so this form
 // trims instructions without changing any result:
@@ -560,6 +662,20 @@ hipError_t launch_sep_e(const GenArgs& a, hipStream_t s) {
   return launch_sep_j<EVAL, false>(a, s);
 }
 
+template <int LPI>
+hipError_t launch_resident_t(const GenArgs& a, int n_gens, float* pop_final,
+                             float* fit_final, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_sep_resident<LPI>);
+  const hipError_t e = set_max_dynamic_lds(fn);
+  if (e != hipSuccess) return e;
+  int threads = ((a.NP * LPI + 63) / 64) * 64;
+  threads = std::min(std::max(threads, 64), 1024);
+  hipLaunchKernelGGL((k_sep_resident<LPI>), dim3(a.runs), dim3(threads),
+                     sep_resident_lds_bytes(a.NP, a.ldx, a.D), s, a, n_gens,
+                     pop_final, fit_final);
+  return hipGetLastError();
+}
+
 template <class P, int BM, int NT, bool EVAL, bool JDE = false>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   const size_t lds = rot_lds_bytes<P, BM, JDE>(a.dpad);
@@ -625,6 +741,30 @@ size_t rot_lds_bytes_host(int prec, int dpad, bool jde) {
 }
 
 bool sep_supported(int D) { return (D + 3) / 4 <= 1024; }
+
+size_t sep_resident_lds_bytes(int NP, int ldx, int D) {
+  return ((size_t)2 * NP * ldx + (size_t)2 * NP + (size_t)(D + 3) / 4 * 4) *
+         sizeof(float);
+}
+
+bool sep_resident_fits(int NP, int ldx, int D) {
+  return (D + 3) / 4 <= 64 &&
+         sep_resident_lds_bytes(NP, ldx, D) <= kSepResidentMaxLds;
+}
+
+hipError_t launch_sep_resident(const GenArgs& a, int n_gens, float* pop_final,
+                               float* fit_final, hipStream_t s) {
+  const int nq = (a.D + 3) / 4;
+  if (nq <= 4) return launch_resident_t<4>(a, n_gens, pop_final, fit_final, s);
+  if (nq <= 8) return launch_resident_t<8>(a, n_gens, pop_final, fit_final, s);
+  if (nq <= 16)
+    return launch_resident_t<16>(a, n_gens, pop_final, fit_final, s);
+  if (nq <= 32)
+    return launch_resident_t<32>(a, n_gens, pop_final, fit_final, s);
+  if (nq <= 64)
+    return launch_resident_t<64>(a, n_gens, pop_final, fit_final, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t set_max_dynamic_lds(const void* fn) {
   int dev = 0;

@@ -34,15 +34,21 @@ __device__ __forceinline__ void set(float4& v, int b, float s) {
 
 // Statistics after an accepted trial with value f of individual i in run r,
 // which produced generation gen+1.
-__device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
-                                              float f) {
+__device__ __forceinline__ void record_accept_at(const GenArgs& a, int run,
+                                                 int i, float f,
+                                                 uint32_t gen) {
   atomicAdd(&a.accepted[run], 1ull);
   atomicMin(&a.best_key[run], fit_key(f, i));
   if (f <= a.target) {
     const unsigned long long old =
-        atomicMin(&a.hit_gen[run], (unsigned long long)a.gen + 1ull);
+        atomicMin(&a.hit_gen[run], (unsigned long long)gen + 1ull);
     if (old == kNoHit) atomicAdd(a.done, 1u);
   }
+}
+
+__device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
+                                              float f) {
+  record_accept_at(a, run, i, f, a.gen);
 }
 
 // ---------------------------------------------------------------------------

@@ -442,3 +442,27 @@ def test_destroyed_handle_and_bad_calls():
     with pytest.raises(d.DEError) as e:
         d.de_generation(h, 1, 0)
     assert e.value.status == d.DE_E_STATE
+
+
+@pytest.mark.parametrize("runs,NP,D,ldx", [(1, 64, 10, None), (3, 37, 13, 20),
+                                           (30, 64, 10, None), (2, 60, 100, None),
+                                           (5, 4, 1, None), (2, 30, 256, None)])
+def test_resident_separable_equals_per_generation(runs, NP, D, ldx):
+    # calls of several generations on small separable problems keep each
+    # run's population in LDS; single generations use the per-generation
+    # kernel: both must agree bit for bit, statistics included
+    a, _, _ = make_de(runs=runs, NP=NP, D=D, seed=3, ldx=ldx)
+    b, _, _ = make_de(runs=runs, NP=NP, D=D, seed=3, ldx=ldx)
+    a.generation(37)
+    a.generation(2)
+    for _ in range(39):
+        b.generation(1)
+    np.testing.assert_array_equal(host(a.population()), host(b.population()))
+    np.testing.assert_array_equal(host(a.fitness()), host(b.fitness()))
+    assert a.stats() == b.stats()
+    # a per-generation step after a resident call rewrites rows correctly
+    a.generation(1)
+    b.generation(1)
+    np.testing.assert_array_equal(host(a.population()), host(b.population()))
+    a.close()
+    b.close()
