@@ -637,22 +637,24 @@ hipError_t launch_sep_row_t(const GenArgs& a, hipStream_t s) {
 template <bool EVAL, bool JDE>
 hipError_t launch_sep_j(const GenArgs& a, hipStream_t s) {
   const int nq = (a.D + 3) / 4;
-  if (!EVAL && nq > 64) {
-    if (nq <= 128) return launch_sep_row_t<2, JDE>(a, s);
-    if (nq <= 256) return launch_sep_row_t<4, JDE>(a, s);
-    if (nq <= 512) return launch_sep_row_t<8, JDE>(a, s);
-    if (nq <= 1024) return launch_sep_row_t<16, JDE>(a, s);
-    return hipErrorInvalidValue;
-  }
   if (nq <= 4) return launch_sep_t<4, 1, EVAL, JDE>(a, s);
   if (nq <= 8) return launch_sep_t<8, 1, EVAL, JDE>(a, s);
   if (nq <= 16) return launch_sep_t<16, 1, EVAL, JDE>(a, s);
   if (nq <= 32) return launch_sep_t<32, 1, EVAL, JDE>(a, s);
   if (nq <= 64) return launch_sep_t<64, 1, EVAL, JDE>(a, s);
-  if (nq <= 128) return launch_sep_t<64, 2, EVAL, JDE>(a, s);
-  if (nq <= 256) return launch_sep_t<64, 4, EVAL, JDE>(a, s);
-  if (nq <= 512) return launch_sep_t<64, 8, EVAL, JDE>(a, s);
-  if (nq <= 1024) return launch_sep_t<64, 16, EVAL, JDE>(a, s);
+  if constexpr (EVAL) {
+    // evaluation only: the wide rows of k_sep
+    if (nq <= 128) return launch_sep_t<64, 2, true, false>(a, s);
+    if (nq <= 256) return launch_sep_t<64, 4, true, false>(a, s);
+    if (nq <= 512) return launch_sep_t<64, 8, true, false>(a, s);
+    if (nq <= 1024) return launch_sep_t<64, 16, true, false>(a, s);
+  } else {
+    // generations of rows over 256 coordinates: one wave per row
+    if (nq <= 128) return launch_sep_row_t<2, JDE>(a, s);
+    if (nq <= 256) return launch_sep_row_t<4, JDE>(a, s);
+    if (nq <= 512) return launch_sep_row_t<8, JDE>(a, s);
+    if (nq <= 1024) return launch_sep_row_t<16, JDE>(a, s);
+  }
   return hipErrorInvalidValue;
 }
 
