@@ -716,16 +716,21 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
   const long long tiles = EVAL ? (a.nrows + 63) / 64
                                : (long long)a.runs * ((a.NP + 63) / 64);
   const bool narrow = rot_bf16_narrow(a.dpad, tiles, device_cus());
+  const bool f32_narrow = a.dpad <= kF32NarrowMaxDpad;
   if (!EVAL && a.jde) {
     if (prec != kPrecBF16)
-      return launch_rot_t<PrecF32, 32, 512, false, true>(a, s);
+      return f32_narrow
+                 ? launch_rot_t<PrecF32Narrow, 32, 512, false, true>(a, s)
+                 : launch_rot_t<PrecF32, 32, 512, false, true>(a, s);
     return narrow
                ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, false,
                               true>(a, s)
                : launch_rot_t<PrecBF16, 64, kRotBf16Threads, false, true>(a,
                                                                           s);
   }
-  if (prec != kPrecBF16) return launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
+  if (prec != kPrecBF16)
+    return f32_narrow ? launch_rot_t<PrecF32Narrow, 32, 512, EVAL>(a, s)
+                      : launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
   return narrow ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, EVAL>(a, s)
                 : launch_rot_t<PrecBF16, 64, kRotBf16Threads, EVAL>(a, s);
 }

@@ -63,14 +63,24 @@ __device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
 //   phase 3: row totals -> selection -> next generation rows (a rejected row
 //            is rewritten only if the other buffer holds a stale copy),
 //            statistics.
+// Operand precision of the rotation product; kOneBlock: each wave owns one
+// 32-column block per pass (BF16 always; FP32 at padded widths up to 256,
+// where two blocks per wave would leave most waves without a block), else
+// two.
 struct PrecBF16 {
   using T = __bf16;
   static constexpr int kPad = 8;  // LDS row padding, elements
+  static constexpr bool kOneBlock = true;
 };
 struct PrecF32 {
   using T = float;
   static constexpr int kPad = 4;
+  static constexpr bool kOneBlock = false;
 };
+struct PrecF32Narrow : PrecF32 {
+  static constexpr bool kOneBlock = true;
+};
+constexpr int kF32NarrowMaxDpad = 256;
 
 // Slots of the per-row objective sums (see rot_tile).
 constexpr int kRotSlots = 16;
@@ -185,6 +195,23 @@ __device__ __forceinline__ void f32_step(const float* ar, int k8, float4 b0,
   c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b1.w, c01, 0, 0, 0);
 }
 
+// Two consecutive FP32 four-step groups (k8, k8 + 1) of one column block
+// into two accumulators, interleaved.
+__device__ __forceinline__ void f32_step2(const float* ar, int k8, float4 b0,
+                                          float4 b1, floatx16& ce,
+                                          floatx16& co) {
+  const float4 a0 = *reinterpret_cast<const float4*>(ar + k8 * 8);
+  const float4 a1 = *reinterpret_cast<const float4*>(ar + (k8 + 1) * 8);
+  ce = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, b0.x, ce, 0, 0, 0);
+  co = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, b1.x, co, 0, 0, 0);
+  ce = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, b0.y, ce, 0, 0, 0);
+  co = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, b1.y, co, 0, 0, 0);
+  ce = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, b0.z, ce, 0, 0, 0);
+  co = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, b1.z, co, 0, 0, 0);
+  ce = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, b0.w, ce, 0, 0, 0);
+  co = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, co, 0, 0, 0);
+}
+
 // One tile: rows row0 .. row0 + nvalid - 1 of run `run` (EVAL: of the
 // flattened row range).  Ends with every LDS access of the tile complete
 // only for the calling thread: a caller that runs another tile in the same
@@ -197,10 +224,10 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   constexpr int kRotThreads = NT;
   constexpr int kRotWaves = NT / 64;
   // BF16 tiles: one column block per wave and pass, four producer rows per
-  // step (128 registers); FP32 tiles: two column blocks, eight rows
-  constexpr int NBW = sizeof(T) == 2 ? 1 : 2;
+  // step (128 registers); FP32 tiles: one or two column blocks (P),
+  // eight rows
+  constexpr int NBW = P::kOneBlock ? 1 : 2;
   static_assert(MB == 1 || (MB == 2 && sizeof(T) == 2), "tile shape");
-  static_assert(NBW == 2 || sizeof(T) == 2, "FP32 tiles use two blocks");
   extern __shared__ __align__(16) char smem[];
   const int dpad = a.dpad;
   const int stride = dpad + P::kPad;
@@ -434,21 +461,38 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       const float4* rop = reinterpret_cast<const float4*>(a.rop);
       const int k8n = dpad / 8;
       const float4* rb0 = rop + ((size_t)nb0 * k8n) * 64 + lane;
-      const float4* rb1 = rb0 + (size_t)k8n * 64;
       const float* ar = reinterpret_cast<const float*>(At) +
                         (size_t)(lane % 32) * stride + 4 * (lane / 32);
-      float4 p00 = rb0[0], p01 = rb0[64], p10 = rb1[0], p11 = rb1[64];
-      for (int k8 = 0; k8 < k8n; k8 += 2) {
-        const float4 q00 = p00, q01 = p01, q10 = p10, q11 = p11;
-        if (k8 + 2 < k8n) {
-          const size_t nx = (size_t)(k8 + 2) * 64;
-          p00 = rb0[nx];
-          p01 = rb0[nx + 64];
-          p10 = rb1[nx];
-          p11 = rb1[nx + 64];
+      if constexpr (NBW == 2) {
+        const float4* rb1 = rb0 + (size_t)k8n * 64;
+        float4 p00 = rb0[0], p01 = rb0[64], p10 = rb1[0], p11 = rb1[64];
+        for (int k8 = 0; k8 < k8n; k8 += 2) {
+          const float4 q00 = p00, q01 = p01, q10 = p10, q11 = p11;
+          if (k8 + 2 < k8n) {
+            const size_t nx = (size_t)(k8 + 2) * 64;
+            p00 = rb0[nx];
+            p01 = rb0[nx + 64];
+            p10 = rb1[nx];
+            p11 = rb1[nx + 64];
+          }
+          f32_step(ar, k8 + 0, q00, q10, c00, c01);
+          f32_step(ar, k8 + 1, q01, q11, c00, c01);
         }
-        f32_step(ar, k8 + 0, q00, q10, c00, c01);
-        f32_step(ar, k8 + 1, q01, q11, c00, c01);
+      } else {
+        // one block: even and odd four-step groups accumulate apart (two
+        // independent MFMA chains), then add
+        float4 p0 = rb0[0], p1 = rb0[64];
+        for (int k8 = 0; k8 < k8n; k8 += 2) {
+          const float4 q0 = p0, q1 = p1;
+          if (k8 + 2 < k8n) {
+            const size_t nx = (size_t)(k8 + 2) * 64;
+            p0 = rb0[nx];
+            p1 = rb0[nx + 64];
+          }
+          f32_step2(ar, k8, q0, q1, c00, c01);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c00[r] += c01[r];
       }
     }
     // The objective of each 32-column block, summed per row and written to
@@ -463,10 +507,12 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     constexpr bool kFastSin = sizeof(T) == 2;
     floatx16& lo = c00;
     floatx16& hi = MB == 2 ? c10 : c01;
+    // FP32 one-block tiles: values 16-31 (a second block) are empty
+    constexpr bool kHi = MB == 2 || NBW == 2;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       lo[r] = osc_term<kFastSin>(lo[r]);
-      hi[r] = osc_term<kFastSin>(hi[r]);
+      hi[r] = kHi ? osc_term<kFastSin>(hi[r]) : 0.f;
     }
     {  // first exchange: values 0-15 keep lo or hi, the other half goes over
       const bool upper = (lane & 16) != 0;
@@ -492,7 +538,8 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       if (pass % SPW == q) sacc[q] += lo[0];
   }
   // lane l holds value l % 32: BF16 row (l % 32 / 16) * 32 + rin of the
-  // wave's blocks; FP32 row rin of block nb0 + (l % 32) / 16
+  // wave's blocks; FP32 row rin of block nb0 + (l % 32) / 16 (one-block
+  // tiles: block nb0 in lanes with l % 32 < 16)
   {
     const int idx = lane % 32, hb = idx / 16, r = idx % 16;
     const int rin = 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
@@ -501,6 +548,8 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       const int b0 = wave * NBW + q * kRotWaves * NBW;  // first block of q
       if constexpr (MB == 2) {
         if (b0 < kRotSlots) fpart[(size_t)b0 * BM + hb * 32 + rin] = sacc[q];
+      } else if constexpr (NBW == 1) {
+        if (hb == 0 && b0 < kRotSlots) fpart[(size_t)b0 * BM + rin] = sacc[q];
       } else {
         if (b0 + hb < kRotSlots)
           fpart[(size_t)(b0 + hb) * BM + rin] = sacc[q];
