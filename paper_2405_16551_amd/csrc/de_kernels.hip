@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
@@ -695,20 +696,24 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Compute units of the current device (queried once).
+// Compute units of the current device (queried once per device and kept
+// in an atomic, so that handles used from several host threads do not race;
+// 256 if the query fails, which only affects the choice of tile width).
 int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
-                              dev) == hipSuccess &&
-        n > 0)
-      cus = n;
-    else
-      return 256;
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> known[kMaxDevices];  // 0: not queried yet
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+  if (dev < kMaxDevices) {
+    n = known[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
   }
-  return cus;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess ||
+      n <= 0)
+    return 256;
+  if (dev < kMaxDevices) known[dev].store(n, std::memory_order_relaxed);
+  return n;
 }
 
 template <bool EVAL>
