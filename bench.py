@@ -18,8 +18,9 @@ separable companion workload
 on the small sphere workload (Section 7.3.4 early stopping), wall time to
 the FP64 oracle's median final best on the rotated D = 100 workload (64
 runs, with the oracle's own time to it extrapolated), a batch of 512
-independent runs of mixed NP, D, F and CR advanced by graph replays, and
-the FP64 CPU oracle timed on a bounded sample of the headline workload.
+independent runs of mixed NP, D, F and CR advanced by graph replays, the
+measured device-copy and library BF16 GEMM ceilings, and the FP64 CPU
+oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -349,6 +350,37 @@ def copy_ceiling(nbytes=1 << 30, reps=20):
                 GBps=round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
 
 
+def gemm_ceiling(reps=20):
+    """BF16 library products (torch.mm, hipBLASLt on ROCm; contiguous 2-D
+    operands, FP32 accumulation) timed with events: a large square product,
+    and the rotation product of the 16-run, NP 1024, D 1000 step alone (16384
+    trial rows x 1024 x 1024 padded, without building the trials, the
+    objective or the selection).  The measured MFMA ceilings next to the
+    2.5 PFLOP/s specification."""
+    import torch
+    out = {}
+    for name, (m, k, n) in (("square_8192", (8192, 8192, 8192)),
+                            ("step_product_16384x1024x1024",
+                             (16384, 1024, 1024))):
+        a = torch.randn(m, k, device="cuda").to(torch.bfloat16).contiguous()
+        b = torch.randn(k, n, device="cuda").to(torch.bfloat16).contiguous()
+        c = torch.mm(a, b)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.mm(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+        out[name] = dict(us=round(ms * 1e3, 2), TFLOPs=round(tf, 1),
+                         frac_of_peak=round(tf / BF16_PEAK_TFLOPS, 4))
+        del a, b, c
+    return out
+
+
 def time_to_target(target=1e-8, max_gens=5000, check_every=50):
     import torch
 
@@ -561,6 +593,7 @@ def main():
         line["time_to_target_c2"] = time_to_target_c2(
             with_oracle=not args.no_cpu_baseline)
         line["copy_ceiling"] = copy_ceiling()
+        line["gemm_ceiling"] = gemm_ceiling()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line), flush=True)
