@@ -100,6 +100,13 @@ def test_unsupported_sizes():
     assert ws_status(P(D=5000), O(kind=0))[0] == d.DE_E_UNSUPPORTED
     assert ws_status(P(D=4096), O(kind=0))[0] == d.DE_OK
     assert ws_status(P(D=1088), O(ldr=1088))[0] == d.DE_OK
+    # the largest supported widths: rotated D = 1152 (padded 1152; the BF16
+    # tile then fills the 160 KB of LDS), separable D = 4096
+    for prec in (0, 1):
+        assert ws_status(P(D=1152), O(prec=prec, ldr=1152))[0] == d.DE_OK
+        assert ws_status(P(D=1153), O(prec=prec, ldr=1153))[0] == \
+            d.DE_E_UNSUPPORTED
+    assert ws_status(P(D=4097), O(kind=0))[0] == d.DE_E_UNSUPPORTED
 
 
 def test_workspace_bytes_layout():

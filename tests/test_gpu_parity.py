@@ -154,6 +154,31 @@ def test_one_generation_bf16_two_tiles_per_cu():
     assert ties <= n // 10
 
 
+@pytest.mark.parametrize("kind,prec,runs,NP,D", [
+    # the largest supported widths: the BF16 tile's LDS is exactly 160 KB at
+    # padded width 1152; separable rows of 4096 fill the one-wave-per-row
+    # form's last chunk exactly
+    ("rot_osc", "bf16", 2, 70, 1152),
+    ("rot_osc", "fp32", 1, 40, 1152),
+    ("sphere", "fp32", 1, 20, 4096),
+])
+def test_one_generation_at_the_largest_supported_width(kind, prec, runs, NP,
+                                                       D):
+    de, o, R = make_de(runs=runs, NP=NP, D=D, seed=5, kind=kind,
+                       gemm_prec=prec)
+    de.generation(2)
+    g = de.gen
+    pop32 = host(de.population()).copy()
+    fit_prev = host(de.fitness()).copy()
+    de.generation(1)
+    rtol = bf16_rtol(D) if prec == "bf16" else FP32_RTOL
+    n, ties = compare_generation(host(de.population()), host(de.fitness()),
+                                 pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
+                                 kind=okind(kind), o=o, R=R, f_rtol=rtol)
+    assert n == runs * NP
+    assert ties <= max(2, n // 10)
+
+
 # ---------------------------------------------------------------------------
 # Objective evaluation through the generation kernels' arithmetic.
 
