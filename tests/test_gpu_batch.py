@@ -142,6 +142,17 @@ def test_wide_tile_threads_do_not_change_results():
     b.close()
 
 
+def test_zero_generations_change_nothing():
+    b, _ = make_batch(graph_gens=4)
+    b.generation(3)
+    before = [host(b.population(r)).copy() for r in range(len(SPECS))]
+    b.generation(0)
+    assert b.gen == 3
+    for r in range(len(SPECS)):
+        np.testing.assert_array_equal(host(b.population(r)), before[r])
+    b.close()
+
+
 def test_graph_replays_equal_direct_launches():
     plan = all_variants(SPECS, 0)
     plan[257] = 2

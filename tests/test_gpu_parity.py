@@ -282,6 +282,22 @@ def test_checkpoint_restart_is_bit_exact(kind, prec):
     np.testing.assert_array_equal(host(a.fitness()), host(c.fitness()))
 
 
+def test_empty_calls_change_nothing():
+    # no generations, an evolve without budget, an evaluation of no rows:
+    # status OK and nothing moves
+    de, o, R = make_de(runs=2, NP=40, D=30, seed=3, kind="rot_osc",
+                       gemm_prec="bf16")
+    de.generation(2)
+    pop, fit = host(de.population()).copy(), host(de.fitness()).copy()
+    de.generation(0)
+    gens, hits = de.evolve(0, target=-1.0)  # a target no run reaches
+    f = de.eval(np.zeros((0, 30), np.float32))
+    assert de.gen == 2 and gens == 0 and hits == [-1, -1]
+    assert host(f).shape == (0,)
+    np.testing.assert_array_equal(host(de.population()), pop)
+    np.testing.assert_array_equal(host(de.fitness()), fit)
+
+
 def test_evolve_stops_at_target_and_records_first_hit():
     runs, NP, D = 3, 64, 10
     de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1)

@@ -249,6 +249,17 @@ def test_screened_generation_matches_oracle(k, warmup):
     s.close()
 
 
+def test_zero_generations_change_nothing():
+    s, _ = make_sur()
+    s.generation(2)
+    pop, fit = host(s.population()).copy(), host(s.fitness()).copy()
+    s.generation(0)
+    assert s.gen == 2
+    np.testing.assert_array_equal(host(s.population()), pop)
+    np.testing.assert_array_equal(host(s.fitness()), fit)
+    s.close()
+
+
 def test_surrogate_runs_make_progress():
     s, _ = make_sur(runs=4, NP=128, D=20, hidden=64, batch=128, archive=2048,
                     warmup_gens=3, steps=2)
