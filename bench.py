@@ -14,7 +14,8 @@ per second, the median and spread of the five segments, the handle's
 initialisation time, the roofline position of the generation kernel (HIP
 events around the K launches, algorithmic FLOPs 2 D^2 per trial), a
 separable companion workload
-(shifted sphere, same sizes; HBM roofline), wall time to the 1e-8 target
+(shifted sphere, same sizes; HBM roofline), the same rotated step with the
+product in FP32, wall time to the 1e-8 target
 on the small sphere workload (Section 7.3.4 early stopping), wall time to
 the FP64 oracle's median final best on the rotated D = 100 workload (64
 runs, with the oracle's own time to it extrapolated), a batch of 512
@@ -581,6 +582,15 @@ def main():
             "gens_per_s": round(c["gens_per_s"], 2),
             "kernel_ms_per_step": round(c["kernel_ms"], 5),
             "accept_rate": c["accept_rate"], "roofline": c["roofline"]}
+        if args.workload == "rot1000_bf16":
+            # the same step with the rotation product in FP32 (the other
+            # GPU arm of this workload; the FP64 oracle is cpu_baseline)
+            f = time_workload("rot1000_fp32", 40, min(args.warmup, 5))
+            line["fp32_product"] = {
+                "workload": describe("rot1000_fp32"),
+                "evals_per_s": round(f["evals_per_s"], 1),
+                "kernel_ms_per_step": round(f["kernel_ms"], 5),
+                "accept_rate": f["accept_rate"], "roofline": f["roofline"]}
         jname = "rot1000_bf16_jde" if w["kind"] == "rot_osc" else "sphere1000_jde"
         j = time_workload(jname, max(50, args.steps // 4), args.warmup)
         line["jde"] = {
