@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_sep(GenArgs a) {
 
 // BF16 tiles of fewer than 1024 threads: two workgroups per CU (four
 // waves per SIMD, 128 registers).
-template <class P, int BM, int NT, bool EVAL, bool JDE>
+template <class P, int BM, int NT, bool EVAL, bool JDE, bool PAIR = false>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(
     (sizeof(typename P::T) == 2 && NT < 1024) ? 4 : 1)))
@@ -151,7 +151,7 @@ void k_rot(GenArgs a) {
     row0 = (lb - run * tiles) * BM;
     nvalid = min(BM, a.NP - row0);
   }
-  rot_tile<P, BM, NT, EVAL, JDE>(a, run, row0, nvalid);
+  rot_tile<P, BM, NT, EVAL, JDE, PAIR>(a, run, row0, nvalid);
 }
 
 // jDE: every individual starts from the same (F, CR).
@@ -679,11 +679,12 @@ hipError_t launch_resident_t(const GenArgs& a, int n_gens, float* pop_final,
   return hipGetLastError();
 }
 
-template <class P, int BM, int NT, bool EVAL, bool JDE = false>
+template <class P, int BM, int NT, bool EVAL, bool JDE = false,
+          bool PAIR = false>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   const size_t lds = rot_lds_bytes<P, BM, JDE>(a.dpad);
   const hipError_t e = set_max_dynamic_lds(
-      reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL, JDE>));
+      reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL, JDE, PAIR>));
   if (e != hipSuccess) return e;
   int blocks;
   if (EVAL) {
@@ -691,8 +692,8 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   } else {
     blocks = a.runs * ((a.NP + BM - 1) / BM);
   }
-  hipLaunchKernelGGL((k_rot<P, BM, NT, EVAL, JDE>), dim3(blocks), dim3(NT),
-                     lds, s, a);
+  hipLaunchKernelGGL((k_rot<P, BM, NT, EVAL, JDE, PAIR>), dim3(blocks),
+                     dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
@@ -733,6 +734,9 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
                : launch_rot_t<PrecBF16, 64, kRotBf16Threads, false, true>(a,
                                                                           s);
   }
+  // padded width up to 128: trials built two rows per wave instruction
+  if (!EVAL && prec != kPrecBF16 && a.dpad <= 128)
+    return launch_rot_t<PrecF32Narrow, 32, 512, false, false, true>(a, s);
   if (prec != kPrecBF16)
     return f32_narrow ? launch_rot_t<PrecF32Narrow, 32, 512, EVAL>(a, s)
                       : launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);

@@ -215,8 +215,10 @@ __device__ __forceinline__ void f32_step2(const float* ar, int k8, float4 b0,
 // One tile: rows row0 .. row0 + nvalid - 1 of run `run` (EVAL: of the
 // flattened row range).  Ends with every LDS access of the tile complete
 // only for the calling thread: a caller that runs another tile in the same
-// workgroup synchronises first.
-template <class P, int BM, int NT, bool EVAL, bool JDE = false>
+// workgroup synchronises first.  PAIR (padded widths up to 128): the trials
+// are built two rows per wave instruction.
+template <class P, int BM, int NT, bool EVAL, bool JDE = false,
+          bool PAIR = false>
 __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
                                          int nvalid) {
   using T = typename P::T;
@@ -272,6 +274,83 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     T* arow = At + (size_t)rl * stride;
     for (int k = lane; k < dpad; k += 64) arow[k] = (T)0.0f;
   }
+  if constexpr (PAIR) {
+    // Padded widths up to 128 (at most 32 quads per row): lanes 32 h + q
+    // build quad q of the h-th row of a pair of the wave's rows, so every
+    // lane has a quad (one row per instruction would leave more than half
+    // of them idle).  Same loads, draws, arithmetic and stores as below;
+    // each row's crossover bits are its half of the ballot.
+    static_assert(!JDE && !EVAL, "paired form: generation step, fixed F, CR");
+    constexpr int RBP = 4;  // pairs per step
+    const int hl = lane / 32, ql = lane % 32;
+    const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
+    const int dlast = ((a.D + 3) / 4 - 1) * 4;
+    const int j0 = 4 * ql, jl = min(j0, dlast);
+    const float4 ov = ld4(a.o + jl);
+    for (int k = 0; k < nrow_w; k += 2 * RBP) {
+      float4 xv[RBP], v1[RBP], v2[RBP], v3[RBP];
+#pragma unroll
+      for (int p = 0; p < RBP; ++p) {
+        const int rl = wave + kRotWaves * min(k + 2 * p + hl, nrow_w - 1);
+        xv[p] = ld4(base + (size_t)(row0 + rl) * a.ldx + jl);
+        if (!EVAL) {
+          v1[p] = ld4(base + (size_t)donors[rl * 4 + 0] * a.ldx + jl);
+          v2[p] = ld4(base + (size_t)donors[rl * 4 + 1] * a.ldx + jl);
+          v3[p] = ld4(base + (size_t)donors[rl * 4 + 2] * a.ldx + jl);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < RBP; ++p) {
+        if (k + 2 * p >= nrow_w) break;
+        const int kk = k + 2 * p + hl;
+        const bool live = kk < nrow_w;  // the pair's second row may not exist
+        const int rl = wave + kRotWaves * min(kk, nrow_w - 1);
+        const int i = row0 + rl;
+        uint32_t bits = 0;
+        float4 uu = xv[p];
+        if (!EVAL) {
+          const int jrand = donors[rl * 4 + 3];
+          const Words4 w = draw_block(kTagXover, rng_run, a.gen, (uint32_t)i,
+                                      (uint32_t)ql, a.key_lo, a.key_hi);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const bool tk = (j0 + b < a.D) &&
+                            take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold);
+            const float mv = mutant_coord(get(v1[p], b), get(v2[p], b),
+                                          get(v3[p], b), a.F, a.lo, a.hi);
+            set(uu, b, tk ? mv : get(xv[p], b));
+            bits |= (tk ? 1u : 0u) << b;
+          }
+        }
+        float4 y;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          set(y, b, (j0 + b < a.D) ? get(uu, b) - get(ov, b) : 0.f);
+        T* arow = At + (size_t)rl * stride;
+        if (live && j0 < dpad) {
+          if constexpr (sizeof(T) == 2) {
+            bf16x4 yb;
+            yb[0] = (__bf16)y.x;
+            yb[1] = (__bf16)y.y;
+            yb[2] = (__bf16)y.z;
+            yb[3] = (__bf16)y.w;
+            *reinterpret_cast<bf16x4*>(arow + j0) = yb;
+          } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) arow[lds_col<P>(j0 + b)] = get(y, b);
+          }
+        }
+        if (!EVAL) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const unsigned long long m = __ballot((bits >> b) & 1u);
+            if (ql == 0 && live)
+              planes[(size_t)rl * tq * 4 + b] = hl ? (m >> 32) : (m & 0xFFFFFFFFull);
+          }
+        }
+      }
+    }
+  } else
   {
     // Chunk-major: for each group of CG 256-coordinate chunks, the wave's
     // rows rl = wave + kRotWaves * k go RB at a time (CG * RB = 8 chunk
@@ -559,6 +638,51 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
   __syncthreads();
 
   // ---- phase 3: selection and the next generation
+  if constexpr (PAIR) {
+    // two rows per wave instruction as in the build: lanes 32 h + q handle
+    // quad q of the h-th row of a pair; lanes 0 and 32 each write their
+    // row's value, flag and statistics
+    const int hl = lane / 32, ql = lane % 32;
+    const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
+    const int dlast = ((a.D + 3) / 4 - 1) * 4;
+    const int j0 = 4 * ql, jl = min(j0, dlast);
+    for (int k = 0; k < nrow_w; k += 2) {
+      const int kk = k + hl;
+      const bool live = kk < nrow_w;
+      const int rl = wave + kRotWaves * min(kk, nrow_w - 1);
+      float f = 0.f;
+#pragma unroll
+      for (int sl = 0; sl < kRotSlots; ++sl) f += fpart[sl * BM + rl];
+      const int i = row0 + rl;
+      const size_t g = (size_t)run * a.NP + i;
+      const float fx = a.fit_cur[g];
+      const bool accept = f < fx;
+      const bool refresh = !accept && a.changed[g] != 0;
+      if (live && (accept || refresh)) {
+        const float4 xv = ld4(base + (size_t)i * a.ldx + jl);
+        float4 out = xv;
+        if (accept) {
+          const float4 v1 = ld4(base + (size_t)donors[rl * 4 + 0] * a.ldx + jl);
+          const float4 v2 = ld4(base + (size_t)donors[rl * 4 + 1] * a.ldx + jl);
+          const float4 v3 = ld4(base + (size_t)donors[rl * 4 + 2] * a.ldx + jl);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const unsigned long long m = planes[(size_t)rl * tq * 4 + b];
+            const float mv = mutant_coord(get(v1, b), get(v2, b), get(v3, b),
+                                          a.F, a.lo, a.hi);
+            set(out, b, ((m >> ql) & 1ull) ? mv : get(xv, b));
+          }
+        }
+        if (j0 < a.D) st4(a.pop_next + g * a.ldx + j0, out);
+      }
+      if (live && ql == 0) {
+        a.fit_next[g] = accept ? f : fx;
+        a.changed[g] = accept ? 1 : 0;
+        if (accept) record_accept(a, run, i, f);
+      }
+    }
+    return;
+  }
   for (int rl = wave; rl < nvalid; rl += kRotWaves) {
     float f = 0.f;
 #pragma unroll
