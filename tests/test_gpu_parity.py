@@ -103,6 +103,11 @@ def test_debug_draws_bit_exact(runs, NP, D, CR):
     ("rot_osc", "fp32", 2, 70, 100, 0.9),
     ("rot_osc", "fp32", 1, 40, 13, 0.3),
     ("rot_osc", "fp32", 1, 65, 250, 0.9),
+    # paired rows (padded width <= 128): a last tile of 24 rows leaves each
+    # wave three (one pair without its second row); D = 128 fills all 32
+    # quads of a row
+    ("rot_osc", "fp32", 2, 88, 100, 0.9),
+    ("rot_osc", "fp32", 1, 50, 128, 0.5),
 ])
 def test_one_generation_matches_oracle(kind, prec, runs, NP, D, CR):
     de, o, R = make_de(runs=runs, NP=NP, D=D, CR=CR, seed=5, kind=kind,
