@@ -735,8 +735,14 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
                                                                           s);
   }
   // padded width up to 128: trials built two rows per wave instruction
-  if (!EVAL && prec != kPrecBF16 && a.dpad <= 128)
-    return launch_rot_t<PrecF32Narrow, 32, 512, false, false, true>(a, s);
+  if (!EVAL && a.dpad <= 128) {
+    if (prec != kPrecBF16)
+      return launch_rot_t<PrecF32Narrow, 32, 512, false, false, true>(a, s);
+    return narrow ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, false,
+                                 false, true>(a, s)
+                  : launch_rot_t<PrecBF16, 64, kRotBf16Threads, false, false,
+                                 true>(a, s);
+  }
   if (prec != kPrecBF16)
     return f32_narrow ? launch_rot_t<PrecF32Narrow, 32, 512, EVAL>(a, s)
                       : launch_rot_t<PrecF32, 32, 512, EVAL>(a, s);
