@@ -724,6 +724,15 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
   const bool narrow = rot_bf16_narrow(a.dpad, tiles, device_cus());
   const bool f32_narrow = a.dpad <= kF32NarrowMaxDpad;
   if (!EVAL && a.jde) {
+    // padded width up to 128: trials built two rows per wave instruction
+    if (a.dpad <= 128) {
+      if (prec != kPrecBF16)
+        return launch_rot_t<PrecF32Narrow, 32, 512, false, true, true>(a, s);
+      return narrow ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, false,
+                                   true, true>(a, s)
+                    : launch_rot_t<PrecBF16, 64, kRotBf16Threads, false, true,
+                                   true>(a, s);
+    }
     if (prec != kPrecBF16)
       return f32_narrow
                  ? launch_rot_t<PrecF32Narrow, 32, 512, false, true>(a, s)

@@ -280,7 +280,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
     // lane has a quad (one row per instruction would leave more than half
     // of them idle).  Same loads, draws, arithmetic and stores as below;
     // each row's crossover bits are its half of the ballot.
-    static_assert(!JDE && !EVAL, "paired form: generation step, fixed F, CR");
+    static_assert(!EVAL, "paired form: generation step");
     constexpr int RBP = 4;  // pairs per step
     const int hl = lane / 32, ql = lane % 32;
     const int nrow_w = wave < nvalid ? (nvalid - 1 - wave) / kRotWaves + 1 : 0;
@@ -310,14 +310,21 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
         float4 uu = xv[p];
         if (!EVAL) {
           const int jrand = donors[rl * 4 + 3];
+          float Fr = a.F;
+          uint32_t crt = a.cr_threshold;
+          if constexpr (JDE) {  // the row's own F', CR'
+            const Control c = ctl[rl];
+            Fr = c.F;
+            crt = cr_threshold_of(c.CR);
+          }
           const Words4 w = draw_block(kTagXover, rng_run, a.gen, (uint32_t)i,
                                       (uint32_t)ql, a.key_lo, a.key_hi);
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const bool tk = (j0 + b < a.D) &&
-                            take_mutant(w.w[b], j0 + b, jrand, a.cr_threshold);
+                            take_mutant(w.w[b], j0 + b, jrand, crt);
             const float mv = mutant_coord(get(v1[p], b), get(v2[p], b),
-                                          get(v3[p], b), a.F, a.lo, a.hi);
+                                          get(v3[p], b), Fr, a.lo, a.hi);
             set(uu, b, tk ? mv : get(xv[p], b));
             bits |= (tk ? 1u : 0u) << b;
           }
@@ -658,6 +665,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       const float fx = a.fit_cur[g];
       const bool accept = f < fx;
       const bool refresh = !accept && a.changed[g] != 0;
+      const float Fr = JDE ? ctl[rl].F : a.F;
       if (live && (accept || refresh)) {
         const float4 xv = ld4(base + (size_t)i * a.ldx + jl);
         float4 out = xv;
@@ -669,7 +677,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
           for (int b = 0; b < 4; ++b) {
             const unsigned long long m = planes[(size_t)rl * tq * 4 + b];
             const float mv = mutant_coord(get(v1, b), get(v2, b), get(v3, b),
-                                          a.F, a.lo, a.hi);
+                                          Fr, a.lo, a.hi);
             set(out, b, ((m >> ql) & 1ull) ? mv : get(xv, b));
           }
         }
@@ -678,6 +686,11 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
       if (live && ql == 0) {
         a.fit_next[g] = accept ? f : fx;
         a.changed[g] = accept ? 1 : 0;
+        if constexpr (JDE) {
+          // the trial's F', CR' survive only with the trial
+          a.jp_next[g] = accept ? make_float2(ctl[rl].F, ctl[rl].CR)
+                                : a.jp_cur[g];
+        }
         if (accept) record_accept(a, run, i, f);
       }
     }
