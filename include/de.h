@@ -163,11 +163,21 @@ DE_API de_status de_generation(de_state* state, int32_t n_gens, void* hip_stream
 
 /* Run until every run's best value is <= target or max_gens further
  * generations have run (Section 7.3.4: budget or error threshold).  The
- * host polls once every check_every (>= 1) generations; the first-hit
- * generation is recorded on the device and is exact whatever check_every
- * is.  *gens_done receives the number of generations run by this call;
- * hit_gen (nullable, runs entries) receives per run the first generation at
- * which the best was <= target, or -1.  Synchronises hip_stream.            */
+ * generations are queued in chunks of check_every (>= 1); behind each
+ * chunk the device's count of runs at the target is copied to pinned host
+ * memory (the solution-found flag of Section 8, copied asynchronously), and
+ * the next chunk is queued before the host reads the previous chunk's
+ * count, so the device does not wait on the host between chunks.  The call
+ * therefore stops at most one chunk after the chunk in which the last run
+ * reached the target: with h the generation at which every run had hit,
+ * gens_done <= h + 2 * check_every - 1 (counted from the call's start), and
+ * no generation is run when every run is at the target already.  The
+ * first-hit generation is recorded on the device and is exact whatever
+ * check_every is.  *gens_done receives the number of generations run by
+ * this call; hit_gen (nullable, runs entries) receives per run the first
+ * generation at which the best was <= target, or -1.  The handle keeps two
+ * pinned host words and two events for the polling from its first
+ * de_evolve call until de_destroy.  Synchronises hip_stream.               */
 DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
                     int32_t check_every, void* hip_stream, int64_t* gens_done,
                     int64_t* hit_gen);

@@ -2,7 +2,7 @@
  * de_surrogate.h -- surrogate-assisted DE/rand/1/bin on a composition
  * objective (libde.so, same library and conventions as de.h).
  *
- * The objective is a composition function (Section 7.3.1 of arXiv
+ * The objective is a composition function (Section 7.3.3 of arXiv
  * 2405.16551): n rotated oscillating components g_k with shifts O[k] and
  * rotations R[k], biases bias[k] and normalised weights,
  *     f(x) = sum_k omega_k (g_k(x) + bias_k),

@@ -27,6 +27,11 @@
  *
  * Precision: every floating-point step is FP64 (the paper fixes none).
  * Summation runs in index order j = 0 .. D-1.
+ *
+ * Parity unpinned: the jDE constants (Brest et al.'s; the paper prints
+ * none) and the surrogate's network and training configuration (not in
+ * the paper).  Every other function is pinned by the tests against the
+ * mathematics or an independent implementation.
  */
 #include <math.h>
 #include <stdint.h>
@@ -267,7 +272,9 @@ void oracle_generation(int runs, int run0, int NP, int D, double F, double CR,
  * variants of Section 2; the GPU code cujDE of Section 8.2).  The rule and
  * its constants are those of Brest, Greiner, Boskovic, Mernik & Zumer,
  * "Self-adapting control parameters in differential evolution" (IEEE TEVC
- * 2006), not of the paper.  Before building its trial, individual i draws
+ * 2006), not of the paper: the constants are parity unpinned against the
+ * paper (the tests pin only the rule's structure).  Before building its
+ * trial, individual i draws
  * four uniforms u1..u4 (one Philox block, tag 4, group 0) and takes
  *     F'  = F_lo + u1 * F_span   if u2 < tau_F,   else F_i
  *     CR' = u3                   if u4 < tau_CR,  else CR_i
@@ -393,7 +400,7 @@ int oracle_run(int runs, int NP, int D, double F, double CR, double lo,
 }
 
 /* ---------------------------------------------------------------------- */
-/* Composition objective (Section 7.3.1, composition functions):
+/* Composition objective (Section 7.3.3, composition functions):
  *     f(x) = sum_k omega_k (g_k(x) + bias_k),  omega_k = w_k / sum_j w_j,
  * g_k the rotated oscillating function with shift O[k] and rotation R[k]
  * (D x D row-major, k-th block of R).  Weights, as in the surrogate

@@ -85,6 +85,11 @@ struct de_state {
   int jde;
   float jF_lo, jF_span;
   uint32_t jtau_F, jtau_CR;
+  // de_evolve's overlapped polling: two pinned host slots for the device's
+  // done counter and the events that mark their copies; created on the
+  // first de_evolve call, released by de_destroy
+  unsigned int* poll_slot;
+  hipEvent_t poll_ev[2];
 };
 
 namespace {
@@ -506,18 +511,55 @@ DE_API de_status de_evolve(de_state* state, int64_t max_gens, double target,
   }
   state->target = t32;
   int64_t done_gens = 0;
-  while (rc == DE_OK) {
-    unsigned int done = 0;
-    rc = FROM_HIP(hipMemcpyAsync(&done, a.done, sizeof(done),
+  if (rc == DE_OK && !state->poll_slot) {
+    void* h = nullptr;
+    rc = FROM_HIP(hipHostMalloc(&h, 2 * sizeof(unsigned int),
+                                hipHostMallocDefault));
+    for (int k = 0; k < 2 && rc == DE_OK; ++k)
+      rc = FROM_HIP(hipEventCreateWithFlags(&state->poll_ev[k],
+                                            hipEventDisableTiming));
+    state->poll_slot = static_cast<unsigned int*>(h);
+  }
+  // Runs already at the target before any generation: read synchronously.
+  unsigned int* slot = state->poll_slot;
+  if (rc == DE_OK) {
+    rc = FROM_HIP(hipMemcpyAsync(&slot[0], a.done, sizeof(unsigned int),
                                  hipMemcpyDeviceToHost, st));
     if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
-    if (rc != DE_OK) break;
-    if ((int)done >= state->p.runs || done_gens >= max_gens) break;
-    const int64_t n = std::min<int64_t>(check_every, max_gens - done_gens);
-    rc = run_generations(state, n, st);
-    done_gens += n;
+  }
+  if (rc == DE_OK && (int)slot[0] < state->p.runs) {
+    // Overlapped polling (the solution-found flag copied to the host behind
+    // every chunk): each chunk of check_every generations is followed on
+    // the stream by a copy of the done counter into a pinned slot and an
+    // event; the next chunk is queued before the host waits for the
+    // previous chunk's event, so the device never idles on the host's round
+    // trip.  The price is at most one chunk run past the chunk in which the
+    // last run hit (the first-hit generations are exact on the device).
+    int inflight = 0, head = 0, tail = 0;
+    while (rc == DE_OK) {
+      while (rc == DE_OK && inflight < 2 && done_gens < max_gens) {
+        const int64_t n = std::min<int64_t>(check_every, max_gens - done_gens);
+        rc = run_generations(state, n, st);
+        if (rc != DE_OK) break;
+        done_gens += n;
+        rc = FROM_HIP(hipMemcpyAsync(&slot[tail], a.done, sizeof(unsigned int),
+                                     hipMemcpyDeviceToHost, st));
+        if (rc == DE_OK) rc = FROM_HIP(hipEventRecord(state->poll_ev[tail], st));
+        tail ^= 1;
+        ++inflight;
+      }
+      if (rc != DE_OK || inflight == 0) break;
+      rc = FROM_HIP(hipEventSynchronize(state->poll_ev[head]));
+      if (rc != DE_OK) break;
+      const unsigned int done = slot[head];
+      head ^= 1;
+      --inflight;
+      if ((int)done >= state->p.runs) break;
+    }
   }
   state->target = -std::numeric_limits<float>::infinity();
+  // a chunk queued ahead may still run: the call returns with the stream idle
+  if (rc == DE_OK) rc = FROM_HIP(hipStreamSynchronize(st));
   *gens_done = done_gens;
   if (rc == DE_OK && hit_gen) {
     const int runs = state->p.runs;
@@ -677,6 +719,9 @@ DE_API de_status de_destroy(de_state* state) {
     g_live.erase(state);
   }
   state->magic = 0;
+  for (int k = 0; k < 2; ++k)
+    if (state->poll_ev[k]) (void)hipEventDestroy(state->poll_ev[k]);
+  if (state->poll_slot) (void)hipHostFree(state->poll_slot);
   delete state;
   return DE_OK;
 }

@@ -682,6 +682,8 @@ hipError_t launch_resident_t(const GenArgs& a, int n_gens, float* pop_final,
 template <class P, int BM, int NT, bool EVAL, bool JDE = false,
           bool PAIR = false>
 hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
+  // the paired-row form covers rows of at most 32 quads (kPairMaxDpad)
+  if (PAIR && a.dpad > kPairMaxDpad) return hipErrorInvalidValue;
   const size_t lds = rot_lds_bytes<P, BM, JDE>(a.dpad);
   const hipError_t e = set_max_dynamic_lds(
       reinterpret_cast<const void*>(&k_rot<P, BM, NT, EVAL, JDE, PAIR>));
@@ -725,7 +727,7 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
   const bool f32_narrow = a.dpad <= kF32NarrowMaxDpad;
   if (!EVAL && a.jde) {
     // padded width up to 128: trials built two rows per wave instruction
-    if (a.dpad <= 128) {
+    if (a.dpad <= kPairMaxDpad) {
       if (prec != kPrecBF16)
         return launch_rot_t<PrecF32Narrow, 32, 512, false, true, true>(a, s);
       return narrow ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, false,
@@ -744,7 +746,7 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
                                                                           s);
   }
   // padded width up to 128: trials built two rows per wave instruction
-  if (!EVAL && a.dpad <= 128) {
+  if (!EVAL && a.dpad <= kPairMaxDpad) {
     if (prec != kPrecBF16)
       return launch_rot_t<PrecF32Narrow, 32, 512, false, false, true>(a, s);
     return narrow ? launch_rot_t<PrecBF16, 64, kRotBf16ThreadsNarrow, false,

@@ -8,7 +8,7 @@
 //                  32x32x16 MFMA with FP32 accumulation, bias and ReLU
 //                  fused; one workgroup per 32 candidates
 //   k_sur_select   per target the lowest prediction is evaluated on the
-//                  composition objective (Section 7.3.1 composition
+//                  composition objective (Section 7.3.3 composition
 //                  functions; the expensive step), strict selection, next
 //                  generation, statistics, archive insert
 // then `steps` Adam steps of every run's model (FP32):

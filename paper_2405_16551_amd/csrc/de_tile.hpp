@@ -212,11 +212,16 @@ __device__ __forceinline__ void f32_step2(const float* ar, int k8, float4 b0,
   co = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, co, 0, 0, 0);
 }
 
+// Widest padded row of the paired-row form: 32 quads, so that one row's
+// quads fill half a wave and its crossover bits are one 32-bit half of a
+// ballot.  Launchers refuse PAIR beyond it.
+constexpr int kPairMaxDpad = 128;
+
 // One tile: rows row0 .. row0 + nvalid - 1 of run `run` (EVAL: of the
 // flattened row range).  Ends with every LDS access of the tile complete
 // only for the calling thread: a caller that runs another tile in the same
-// workgroup synchronises first.  PAIR (padded widths up to 128): the trials
-// are built two rows per wave instruction.
+// workgroup synchronises first.  PAIR (padded widths up to kPairMaxDpad
+// only): the trials are built two rows per wave instruction.
 template <class P, int BM, int NT, bool EVAL, bool JDE = false,
           bool PAIR = false>
 __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,

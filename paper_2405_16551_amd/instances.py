@@ -79,7 +79,7 @@ COMPOSITION_SIGMA = 50.0
 
 
 def make_composition(D: int, n: int = 8, obj_seed: int = 1):
-    """Composition of n rotated oscillating components (Section 7.3.1
+    """Composition of n rotated oscillating components (Section 7.3.3
     composition functions): shifts O [n, D] ~ U[-80, 80], Haar rotations
     R [n, D, D] (float32), biases 100 k (the component with the smallest
     bias holds the global optimum, as in the paper's definition), weight

@@ -6,6 +6,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -294,3 +295,30 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_binding_binds_to_one_hip_runtime():
+    # libde.so links against the HIP runtime; PyTorch ships its own copy.
+    # Loading the library before PyTorch left a process with two HIP
+    # runtimes, which crashed at the first device call.  The binding imports
+    # PyTorch first: in a fresh interpreter, torch must be imported when the
+    # library is loaded, and exactly one HIP runtime may be mapped after it.
+    code = f"""
+import ctypes, sys
+sys.path.insert(0, {ROOT!r})
+seen = []
+_orig = ctypes.CDLL.__init__
+def _init(self, name, *a, **k):
+    if name and str(name).endswith("libde.so"):
+        seen.append("torch" in sys.modules)
+    _orig(self, name, *a, **k)
+ctypes.CDLL.__init__ = _init
+import paper_2405_16551_amd.de
+maps = open("/proc/self/maps").read().splitlines()
+hip = sorted({{ln.split()[-1] for ln in maps if "libamdhip64.so" in ln}})
+print(seen, len(hip))
+"""
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True,
+                         text=True, timeout=300, check=True).stdout.split()
+    assert out[0] == "[True]", out
+    assert out[1] == "1", out

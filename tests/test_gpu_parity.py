@@ -22,8 +22,8 @@ import pytest
 
 import oracle
 from tests import de_stats
-from tests.gpu_helpers import (FP32_RTOL, HI, LO, compare_generation, host,
-                               make_de, okind)
+from tests.gpu_helpers import (FP32_RTOL, FP32_TIE_SHARE, HI, LO,
+                               compare_generation, host, make_de, okind)
 
 pytestmark = pytest.mark.gpu
 
@@ -118,10 +118,11 @@ def test_one_generation_matches_oracle(kind, prec, runs, NP, D, CR):
     pop32 = host(de.population()).copy()
     fit_prev = host(de.fitness()).copy()
     de.generation(1)
-    n, ties = compare_generation(host(de.population()), host(de.fitness()),
-                                 pop32, fit_prev, F=0.5, CR=CR, seed=5, gen=g,
-                                 kind=okind(kind), o=o, R=R, f_rtol=FP32_RTOL)
-    assert ties <= max(2, n // 50)
+    res = compare_generation(host(de.population()), host(de.fitness()),
+                             pop32, fit_prev, F=0.5, CR=CR, seed=5, gen=g,
+                             kind=okind(kind), o=o, R=R, f_rtol=FP32_RTOL)
+    assert res.n == runs * NP
+    res.check(f"{kind}/{prec} {runs}x{NP}x{D} CR={CR}", share=FP32_TIE_SHARE)
 
 
 def test_one_generation_bf16_gemm():
@@ -133,17 +134,19 @@ def test_one_generation_bf16_gemm():
     pop32 = host(de.population()).copy()
     fit_prev = host(de.fitness()).copy()
     de.generation(1)
-    n, ties = compare_generation(host(de.population()), host(de.fitness()),
-                                 pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
-                                 kind=oracle.OBJ_ROT_OSC, o=o, R=R,
-                                 f_rtol=bf16_rtol(D))
-    assert ties <= n // 10
+    res = compare_generation(host(de.population()), host(de.fitness()),
+                             pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
+                             kind=oracle.OBJ_ROT_OSC, o=o, R=R,
+                             f_rtol=bf16_rtol(D))
+    res.check(f"rot_osc/bf16 {runs}x{NP}x{D}")
 
 
-def test_one_generation_bf16_two_tiles_per_cu():
-    # more 64-row tiles than compute units at a padded width of 256: the
-    # BF16 tile runs with 512 threads, two workgroups per CU
-    runs, NP, D = 2, 8256, 256
+@pytest.mark.parametrize("D", [256, 100])
+def test_one_generation_bf16_two_tiles_per_cu(D):
+    # more 64-row tiles (258) than compute units: the BF16 tile runs with
+    # 512 threads, two workgroups per CU; at D = 100 (padded width 128) in
+    # the paired-row form (trials built two rows per wave instruction)
+    runs, NP = 2, 8256
     de, o, R = make_de(runs=runs, NP=NP, D=D, seed=5, kind="rot_osc",
                        gemm_prec="bf16")
     de.generation(2)
@@ -151,12 +154,12 @@ def test_one_generation_bf16_two_tiles_per_cu():
     pop32 = host(de.population()).copy()
     fit_prev = host(de.fitness()).copy()
     de.generation(1)
-    n, ties = compare_generation(host(de.population()), host(de.fitness()),
-                                 pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
-                                 kind=oracle.OBJ_ROT_OSC, o=o, R=R,
-                                 f_rtol=bf16_rtol(D))
-    assert n == runs * NP
-    assert ties <= n // 10
+    res = compare_generation(host(de.population()), host(de.fitness()),
+                             pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
+                             kind=oracle.OBJ_ROT_OSC, o=o, R=R,
+                             f_rtol=bf16_rtol(D))
+    assert res.n == runs * NP
+    res.check(f"rot_osc/bf16 {runs}x{NP}x{D} (512-thread tiles)")
 
 
 @pytest.mark.parametrize("kind,prec,runs,NP,D", [
@@ -177,11 +180,11 @@ def test_one_generation_at_the_largest_supported_width(kind, prec, runs, NP,
     fit_prev = host(de.fitness()).copy()
     de.generation(1)
     rtol = bf16_rtol(D) if prec == "bf16" else FP32_RTOL
-    n, ties = compare_generation(host(de.population()), host(de.fitness()),
-                                 pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
-                                 kind=okind(kind), o=o, R=R, f_rtol=rtol)
-    assert n == runs * NP
-    assert ties <= max(2, n // 10)
+    res = compare_generation(host(de.population()), host(de.fitness()),
+                             pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
+                             kind=okind(kind), o=o, R=R, f_rtol=rtol)
+    assert res.n == runs * NP
+    res.check(f"{kind}/{prec} {runs}x{NP}x{D}")
 
 
 # ---------------------------------------------------------------------------
@@ -230,6 +233,10 @@ def test_bf16_error_is_stated():
 # Multi-generation behaviour.
 
 def test_teacher_forced_trajectory_sphere():
+    # generations 250 and 399 lie past the 1e-8 hit (generation ~280): there
+    # the FP32 rounding of a trial's coordinates (~1e-5 at |x| ~ 80) moves f
+    # by more than f itself, so selection is a near-tie for most rows and
+    # only the rows' contents are checked; earlier generations are decided
     runs, NP, D, G = 2, 64, 10, 400
     de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1)
     checkpoints = {0, 1, 10, 100, 250, 399}
@@ -238,10 +245,14 @@ def test_teacher_forced_trajectory_sphere():
             pop32 = host(de.population()).copy()
             fit_prev = host(de.fitness()).copy()
             de.generation(1)
-            compare_generation(host(de.population()), host(de.fitness()), pop32,
-                               fit_prev, F=0.5, CR=0.9, seed=1, gen=g,
-                               kind=oracle.OBJ_SPHERE, o=o, R=None,
-                               f_rtol=FP32_RTOL)
+            res = compare_generation(host(de.population()), host(de.fitness()),
+                                     pop32, fit_prev, F=0.5, CR=0.9, seed=1,
+                                     gen=g, kind=oracle.OBJ_SPHERE, o=o,
+                                     R=None, f_rtol=FP32_RTOL)
+            if g <= 100:
+                res.check(f"sphere trajectory gen {g}", share=FP32_TIE_SHARE)
+            else:
+                res.report(f"sphere trajectory gen {g} (past the optimum)")
         else:
             de.generation(1)
 
@@ -309,7 +320,9 @@ def test_evolve_stops_at_target_and_records_first_hit():
     ref, _, _ = make_de(runs=runs, NP=NP, D=D, seed=1)
     gens_done, hits = de.evolve(2000, target=1e-8, check_every=64)
     assert all(h > 0 for h in hits)
-    assert max(hits) <= gens_done < max(hits) + 64
+    # the chunk after the one in which the last run hit may have run too
+    assert max(hits) <= gens_done < max(hits) + 2 * 64
+    assert gens_done % 64 == 0
     # replay generation by generation: first generation with best <= 1e-8
     first = [-1] * runs
     for g in range(1, max(hits) + 1):
@@ -413,62 +426,82 @@ def test_c2_distribution_full_size():
 
 
 # ---------------------------------------------------------------------------
-# Full-size workloads: sampled rows the oracle computes one by one.
+# Full-size workloads (16 runs x NP 1024 x D 1000, the benchmark's launch
+# configuration): every row of a generation against the oracle, early (the
+# step from generation 1) and late (teacher-forced: the oracle steps the
+# GPU's own population of generation 1500, which the oracle computes in
+# about a second on 16 host threads).
 
-def _sampled_generation_check(kind, prec, runs, NP, D, f_rtol, nsample=48):
-    from tests.gpu_helpers import rounding_band, trial_atol
+@pytest.mark.parametrize("kind,prec,at", [
+    ("sphere", "fp32", 1), ("sphere", "fp32", 1500),
+    ("rot_osc", "bf16", 1), ("rot_osc", "bf16", 1500),
+    ("rot_osc", "fp32", 1), ("rot_osc", "fp32", 1500),
+])
+def test_full_size_every_row(kind, prec, at):
+    runs, NP, D = 16, 1024, 1000
     de, o, R = make_de(runs=runs, NP=NP, D=D, seed=1, kind=kind,
                        gemm_prec=prec)
-    de.generation(1)
+    de.generation(at)
     g = de.gen
     pop32 = host(de.population()).copy()
     fit_prev = host(de.fitness()).copy()
     de.generation(1)
-    pop_next, fit_next = host(de.population()), host(de.fitness())
-    rng = np.random.default_rng(0)
-    rows = [(int(rng.integers(runs)), int(rng.integers(NP)))
-            for _ in range(nsample)]
-    rows += [(0, 0), (runs - 1, NP - 1)]
-    kind_o = okind(kind)
-    flips = 0
-    for r, i in rows:
-        r1, r2, r3, jr = oracle.draw_indices(1, r, g, i, NP, D)
-        x = pop32[r, i].astype(np.float64)
-        p1, p2, p3 = (pop32[r, k].astype(np.float64) for k in (r1, r2, r3))
-        m = np.clip(p1 + 0.5 * (p2 - p3), LO, HI)
-        take = np.array([oracle.take_mutant(1, r, g, i, j, jr, 0.9)
-                         for j in range(D)])
-        u = np.where(take, m, x)
-        fu = oracle.objective(kind_o, u, o, R)
-        fx = oracle.objective(kind_o, x, o, R)
-        assert abs(fit_prev[r, i] - fx) <= f_rtol * fx
-        tol = trial_atol(p1, p2, p3, 0.5)
-        band = f_rtol * max(fu, fx) + rounding_band(kind_o, u, o, R, tol)
-        if abs(fu - fx) <= band:
-            flips += 1
-            continue
-        if fu < fx:
-            assert (np.abs(pop_next[r, i] - u) <= tol).all()
-            f_own = oracle.objective(kind_o, pop_next[r, i].astype(np.float64),
-                                     o, R)
-            assert abs(fit_next[r, i] - f_own) <= f_rtol * f_own
-        else:
-            np.testing.assert_array_equal(pop_next[r, i], pop32[r, i])
-    assert flips <= 2
+    rtol = bf16_rtol(D) if prec == "bf16" else FP32_RTOL
+    res = compare_generation(host(de.population()), host(de.fitness()),
+                             pop32, fit_prev, F=0.5, CR=0.9, seed=1, gen=g,
+                             kind=okind(kind), o=o, R=R, f_rtol=rtol)
+    assert res.n == runs * NP
+    assert res.accepts > 0 and res.rejects > 0
+    res.check(f"{kind}/{prec} 16x1024x1000 gen {g}",
+              share=FP32_TIE_SHARE if prec == "fp32" else None)
 
 
-def test_full_size_separable_sampled():
-    _sampled_generation_check("sphere", "fp32", 16, 1024, 1000, FP32_RTOL)
+# ---------------------------------------------------------------------------
+# Bound repair: F = 2, CR = 1 sends many mutant coordinates out of the box.
+# The box [-10, 10] lies inside the shift's range [-80, 80], so most of the
+# optimum's coordinates are outside it: trials pushed onto the bounds are
+# the good ones, and accepted trials carry many clamped coordinates.
 
-
-def test_full_size_rotated_bf16_sampled():
-    _sampled_generation_check("rot_osc", "bf16", 16, 1024, 1000,
-                              bf16_rtol(1000), nsample=24)
-
-
-def test_full_size_rotated_fp32_sampled():
-    _sampled_generation_check("rot_osc", "fp32", 16, 1024, 1000, FP32_RTOL,
-                              nsample=24)
+@pytest.mark.parametrize("kind,prec,D", [
+    ("sphere", "fp32", 37), ("sphere", "fp32", 600),
+    ("rot_osc", "fp32", 100), ("rot_osc", "bf16", 100),
+    ("rot_osc", "bf16", 300),
+])
+def test_clamped_coordinates_are_the_bounds(kind, prec, D):
+    # every trial coordinate is the mutant x_r1 + 2 (x_r2 - x_r3); where its
+    # exact value lies outside [lo, hi] by more than one FP32 rounding, the
+    # GPU's accepted trial must hold lo or hi exactly
+    runs, NP, F, CR, lo, hi = 2, 128, 2.0, 1.0, -10.0, 10.0
+    de, o, R = make_de(runs=runs, NP=NP, D=D, F=F, CR=CR, seed=8, kind=kind,
+                       gemm_prec=prec, lo=lo, hi=hi)
+    rtol = bf16_rtol(D) if prec == "bf16" else FP32_RTOL
+    clamped = 0
+    for _ in range(3):
+        g = de.gen
+        pop32 = host(de.population()).copy()
+        fit_prev = host(de.fitness()).copy()
+        de.generation(1)
+        pop_n, fit_n = host(de.population()), host(de.fitness())
+        res = compare_generation(pop_n, fit_n, pop32, fit_prev, F=F, CR=CR,
+                                 seed=8, gen=g, kind=okind(kind), o=o, R=R,
+                                 f_rtol=rtol, lo=lo, hi=hi)
+        res.check(f"{kind}/{prec} D={D} F=2 CR=1 gen {g}",
+                  share=FP32_TIE_SHARE if prec == "fp32" else None)
+        pop64 = pop32.astype(np.float64)
+        for r in range(runs):
+            for i in range(NP):
+                if np.array_equal(pop_n[r, i], pop32[r, i]):
+                    continue  # kept
+                r1, r2, r3, _ = oracle.draw_indices(8, r, g, i, NP, D)
+                m = pop64[r, r1] + F * (pop64[r, r2] - pop64[r, r3])
+                tol = 2.0 ** -22 * (np.abs(pop64[r, r1]) + F * (
+                    np.abs(pop64[r, r2]) + np.abs(pop64[r, r3])))
+                below, above = m < lo - tol, m > hi + tol
+                assert (pop_n[r, i][below] == np.float32(lo)).all(), (r, i)
+                assert (pop_n[r, i][above] == np.float32(hi)).all(), (r, i)
+                clamped += int(below.sum() + above.sum())
+    print(f"{kind}/{prec} D={D}: {clamped} clamped coordinates checked")
+    assert clamped > 0
 
 
 # ---------------------------------------------------------------------------

@@ -2,7 +2,7 @@
 against the FP64 oracle, through the C ABI.
 
 Parts and bars:
-  * composition objective (Section 7.3.1 composition functions), FP32:
+  * composition objective (Section 7.3.3 composition functions), FP32:
     within 2e-5 relative of the oracle on the same FP32 rows;
   * initial population bit-exact (same draws as the plain path), its
     fitness and the archive's first round;

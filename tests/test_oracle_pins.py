@@ -561,7 +561,7 @@ def test_jde_trial_uses_the_rows_own_parameters():
 
 
 # --------------------------------------------------------------------------
-# Surrogate-assisted variant: composition objective (Section 7.3.1
+# Surrogate-assisted variant: composition objective (Section 7.3.3
 # composition functions), the MLP surrogate and the pre-screened generation.
 
 def _comp(D=6, n=3, seed=2):
