@@ -268,6 +268,38 @@ DE_API de_status de_eval(de_state* state, const float* x_dev, int32_t n, int32_t
 DE_API de_status de_debug_draws(const de_state* state, int64_t gen, int32_t* idx4_dev,
                          uint32_t* mask_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * generation gen -> gen + 1 of all runs, as de_generation computes it on a
+ * handle at generation gen, without a handle or a workspace.
+ *   pop_cur, fit_cur : generation gen (runs * NP rows of ldx floats, runs * NP
+ *                      values), device, read only;
+ *   pop_next, fit_next: generation gen + 1, device, written (every row);
+ *   ldx >= D, ldx % 4 == 0, row buffers 16-byte aligned, the two populations
+ *   distinct; 0 <= gen < 2^32 - 1.  params and objective as for
+ *   de_init_population (plain DE; o and R are read during the call).
+ * The results equal those of de_generation on a handle holding the same
+ * generation, bit for bit.  The library's own scratch (per-run statistics,
+ * row flags, the padded shift and R in the product's operand layout) lives
+ * in a fixed device array of 8 MiB inside the library, one per GPU, kept
+ * until the process ends; the call allocates nothing and rewrites every
+ * part of that array it uses with kernels (no memset), so it may be
+ * captured into a graph.  Bytes used: sections of 8 runs (three of them),
+ * 4, runs * NP, 4 dpad and, for DE_OBJ_ROT_OSC, dpad^2 * (2 BF16 | 4 FP32),
+ * each rounded up to a multiple of 256, with dpad = D rounded up to 128;
+ * beyond 8 MiB the call returns DE_E_UNSUPPORTED before any device work
+ * (16 runs of NP 1024 at D = 1000 take 2.0 MiB with the BF16 product,
+ * 4.0 MiB with FP32).  Statistics are not
+ * reported.  Calls on one GPU share the array: calls that overlap in time
+ * on one GPU (other streams, other host threads) race and must not be
+ * issued.  Asynchronous on hip_stream.                                     */
+DE_API de_status de_generation_noalloc(const de_params* params,
+                                       const de_objective* objective,
+                                       int64_t gen, const float* pop_cur,
+                                       const float* fit_cur, float* pop_next,
+                                       float* fit_next, int32_t ldx,
+                                       void* hip_stream);
+
 /* Release the handle (host memory only).  NULL is accepted. */
 DE_API de_status de_destroy(de_state* state);
 

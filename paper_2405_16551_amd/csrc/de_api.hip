@@ -19,6 +19,14 @@
 #include "de.h"
 #include "de_internal.h"
 
+// Scratch of de_generation_noalloc: a fixed array in the library's device
+// code, one copy on every GPU the library runs on, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (in
+// host code the name stands for a host-side shadow): it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 using de::GenArgs;
@@ -37,7 +45,10 @@ size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 // eight K-steps of 16.
 int dpad_for(int D) { return (int)round_up((size_t)D, 128); }
 
-Layout layout_for(const de_params& p, int kind, int prec) {
+// handle: the workspace of a handle; otherwise only what one generation
+// step uses (statistics, changed flags, padded shift, R operand layout), the
+// scratch of de_generation_noalloc.
+Layout layout_for(const de_params& p, int kind, int prec, bool handle = true) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -54,10 +65,13 @@ Layout layout_for(const de_params& p, int kind, int prec) {
   L.opad = take(4 * (size_t)dpad);
   L.rop = 0;
   L.rf32 = 0;
-  if (kind == de::kObjRotOsc) {
+  if (kind == de::kObjRotOsc)
     L.rop = take((size_t)dpad * dpad * (prec == de::kPrecBF16 ? 2 : 4));
-    L.rf32 = take((size_t)p.D * p.D * 4);
+  if (!handle) {
+    L.total = off;
+    return L;
   }
+  if (kind == de::kObjRotOsc) L.rf32 = take((size_t)p.D * p.D * 4);
   L.f64 = take(8 * (size_t)p.runs);
   L.idx = take(4 * (size_t)p.runs);
   // jDE control values (F, CR) per individual, generation g and g+1
@@ -65,6 +79,29 @@ Layout layout_for(const de_params& p, int kind, int prec) {
   L.jp[1] = take(8 * (size_t)p.runs * p.NP);
   L.total = off;
   return L;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];  // per device, set on first use
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+hipError_t static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace
@@ -709,6 +746,82 @@ DE_API de_status de_debug_draws(const de_state* state, int64_t gen,
   a.gen = (uint32_t)gen;
   return FROM_HIP(de::launch_debug_draws(
       a, idx4_dev, mask_dev, reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+DE_API de_status de_generation_noalloc(const de_params* params,
+                                       const de_objective* objective,
+                                       int64_t gen, const float* pop_cur,
+                                       const float* fit_cur, float* pop_next,
+                                       float* fit_next, int32_t ldx,
+                                       void* hip_stream) {
+  de_status rc = check_problem(params, objective);
+  if (rc != DE_OK) return rc;
+  const de_params& p = *params;
+  if (gen < 0 || gen + 1 >= kGenLimit) return DE_E_INVAL;
+  if (check_rows(pop_cur, 0, ldx, p.D) != DE_OK ||
+      check_rows(pop_next, 0, ldx, p.D) != DE_OK)
+    return DE_E_INVAL;
+  if (!fit_cur || !fit_next || !aligned(fit_cur, 4) || !aligned(fit_next, 4))
+    return DE_E_INVAL;
+  if (pop_cur == pop_next || fit_cur == fit_next) return DE_E_INVAL;
+  if ((uint64_t)p.runs * p.NP * (uint64_t)ldx >
+      (uint64_t)std::numeric_limits<int64_t>::max() / 4)
+    return DE_E_INVAL;
+  const int prec = objective->kind == de::kObjRotOsc ? objective->gemm_prec
+                                                     : de::kPrecF32;
+  const Layout L = layout_for(p, objective->kind, prec, false);
+  if (L.total > kStaticScratchBytes) return DE_E_UNSUPPORTED;
+
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DE_E_DEVICE;
+  if (objective->kind == de::kObjRotOsc) {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              dev) != hipSuccess)
+      return DE_E_DEVICE;
+    if (de::rot_lds_bytes_host(prec, dpad_for(p.D)) > (size_t)lds)
+      return DE_E_UNSUPPORTED;
+  }
+  void* work = nullptr;
+  rc = FROM_HIP(static_scratch(&work));
+  if (rc != DE_OK) return rc;
+
+  // A handle on the stack over the caller's buffers and the scratch: the
+  // step below is the one de_generation launches, so the results are the
+  // same bit for bit.
+  de_state s{};
+  s.magic = kMagic;
+  s.p = p;
+  s.kind = objective->kind;
+  s.prec = prec;
+  s.dpad = dpad_for(p.D);
+  s.ldx = ldx;
+  const int b = (int)(gen & 1);
+  s.pop[b] = const_cast<float*>(pop_cur);
+  s.fit[b] = const_cast<float*>(fit_cur);
+  s.pop[b ^ 1] = pop_next;
+  s.fit[b ^ 1] = fit_next;
+  s.work = static_cast<char*>(work);
+  s.L = L;
+  s.gen = gen;
+  s.cr_threshold = (uint32_t)std::floor((double)p.CR * 16777216.0);
+  s.target = -std::numeric_limits<float>::infinity();
+  s.last_stream = st;
+  // every section that must start from a known value is rewritten by a
+  // kernel (no memset: the call may be captured into a graph): padded
+  // shift and R operand layout, statistics, and "changed" for every row so
+  // that the step writes every row of pop_next
+  rc = FROM_HIP(de::launch_prep(objective->o, objective->R, objective->ldr,
+                                p.D, s.dpad, s.kind, s.prec,
+                                reinterpret_cast<float*>(s.work + L.opad),
+                                L.rop ? s.work + L.rop : nullptr, st));
+  const GenArgs a = base_args(&s);
+  if (rc == DE_OK) rc = FROM_HIP(de::launch_stats_reset(a, true, st));
+  if (rc == DE_OK) rc = FROM_HIP(de::launch_mark_changed(a, st));
+  if (rc == DE_OK) rc = run_generations(&s, 1, st);
+  return rc;
 }
 
 DE_API de_status de_destroy(de_state* state) {

@@ -25,8 +25,6 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
-#include <set>
-#include <utility>
 
 #include "de_device.hpp"
 #include "de_internal.h"
@@ -803,16 +801,26 @@ hipError_t set_max_dynamic_lds(const void* fn) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
+  // (kernel, device) pairs already set, in a fixed table (no allocation on
+  // any launch path); when it is full the attribute is simply set again
+  constexpr int kSlots = 512;
   static std::mutex mu;
-  static std::set<std::pair<const void*, int>> done;
+  static const void* done_fn[kSlots];
+  static int done_dev[kSlots];
+  static int n_done = 0;
   std::lock_guard<std::mutex> lk(mu);
-  if (done.count({fn, dev})) return hipSuccess;
+  for (int k = 0; k < n_done; ++k)
+    if (done_fn[k] == fn && done_dev[k] == dev) return hipSuccess;
   hipFuncAttributes fa{};
   e = hipFuncGetAttributes(&fa, fn);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kMaxLdsBytes - (int)fa.sharedSizeBytes);
-  if (e == hipSuccess) done.insert({fn, dev});
+  if (e == hipSuccess && n_done < kSlots) {
+    done_fn[n_done] = fn;
+    done_dev[n_done] = dev;
+    ++n_done;
+  }
   return e;
 }
 

@@ -108,6 +108,7 @@ EXPORTS = ("de_abi_version", "de_strerror", "de_workspace_bytes",
            "de_best_f64", "de_get_generation", "de_read_stats", "de_load_population",
            "de_eval", "de_debug_draws", "de_destroy",
            "de_init_population_jde", "de_get_control", "de_set_control",
+           "de_generation_noalloc",
            # include/de_surrogate.h
            "de_sur_model_size", "de_sur_workspace_bytes", "de_sur_init",
            "de_sur_generation", "de_sur_read", "de_sur_get_generation",
@@ -150,6 +151,9 @@ def _load():
     lib.de_set_control.argtypes = [vp, vp, fp, fp]
     lib.de_generation.restype = st
     lib.de_generation.argtypes = [vp, i32, vp]
+    lib.de_generation_noalloc.restype = st
+    lib.de_generation_noalloc.argtypes = [P(de_params), P(de_objective), i64,
+                                          vp, vp, vp, vp, i32, vp]
     lib.de_evolve.restype = st
     lib.de_evolve.argtypes = [vp, i64, ctypes.c_double, i32, vp, P(i64),
                               P(i64)]
@@ -290,6 +294,16 @@ def de_set_control(handle, stream, F, CR):
 
 def de_generation(handle, n_gens: int, stream):
     _check(_lib.de_generation(handle, n_gens, stream), "de_generation")
+
+
+def de_generation_noalloc(params, objective, gen: int, pop_cur, fit_cur,
+                          pop_next, fit_next, ldx: int, stream):
+    """One generation gen -> gen + 1 without a handle or workspace (the
+    library's static scratch); pointers are device addresses (ints)."""
+    _check(_lib.de_generation_noalloc(ctypes.byref(params),
+                                      ctypes.byref(objective), gen, pop_cur,
+                                      fit_cur, pop_next, fit_next, ldx, stream),
+           "de_generation_noalloc")
 
 
 def de_evolve(handle, max_gens: int, target: float, check_every: int, stream,

@@ -33,7 +33,7 @@ def test_every_header_is_covered():
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert len(names) == 38
+    assert len(names) == 39
     assert set(names) == set(d.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", d.LIB_PATH],
                          capture_output=True, text=True, check=True).stdout
@@ -322,3 +322,31 @@ print(seen, len(hip))
                          text=True, timeout=300, check=True).stdout.split()
     assert out[0] == "[True]", out
     assert out[1] == "1", out
+
+
+def _noalloc(p, o, gen=3, pop_cur=1 << 20, fit_cur=3 << 20, pop_next=2 << 20,
+             fit_next=4 << 20, ldx=1000):
+    return d._lib.de_generation_noalloc(ctypes.byref(p), ctypes.byref(o), gen,
+                                        pop_cur, fit_cur, pop_next, fit_next,
+                                        ldx, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(gen=-1), dict(gen=(1 << 32) - 1), dict(pop_cur=None),
+    dict(pop_next=(2 << 20) + 4), dict(pop_next=1 << 20), dict(fit_next=3 << 20),
+    dict(fit_cur=None), dict(ldx=999), dict(ldx=1002)])
+def test_noalloc_step_rejects_bad_arguments(kw):
+    # checked on the host before any device work (no GPU needed)
+    assert _noalloc(P(), O(), **kw) == d.DE_E_INVAL
+    assert _noalloc(P(F=0.0), O()) == d.DE_E_INVAL
+    assert _noalloc(P(), O(R=None)) == d.DE_E_INVAL
+
+
+def test_noalloc_step_scratch_limit():
+    # the static scratch holds 8 MiB: statistics (3 x 8 runs), a flag byte
+    # per row, the padded shift and, rotated, R in the operand layout; a
+    # separable problem of 10 M rows needs 10 MB of row flags
+    assert _noalloc(P(runs=512, NP=20000, D=8), O(kind=0), ldx=8) == \
+        d.DE_E_UNSUPPORTED
+    assert _noalloc(P(runs=64, NP=131072, D=8), O(kind=0), ldx=8) == \
+        d.DE_E_UNSUPPORTED
