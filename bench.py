@@ -18,7 +18,10 @@ separable companion workload
 product in FP32, wall time to the 1e-8 target
 on the small sphere workload (Section 7.3.4 early stopping), wall time to
 the FP64 oracle's median final best on the rotated D = 100 workload (64
-runs, with the oracle's own time to it extrapolated), a batch of 512
+runs, with the oracle's own time to it extrapolated), the headline
+workload as configured (2000 generations in BF16 and FP32: per-step time
+and acceptance over the whole run, median best next to the FP64 oracle's,
+wall time to the oracle's median final best), a batch of 512
 independent runs of mixed NP, D, F and CR advanced by graph replays, the
 measured device-copy and library BF16 GEMM ceilings, and the FP64 CPU
 oracle timed on a bounded sample of the headline workload.
@@ -470,6 +473,101 @@ def time_to_target_c2(with_oracle, max_gens=6000, check_every=50):
     return out
 
 
+def c3_run(with_oracle, max_gens=4000, check_every=50):
+    """The rotated D = 1000 workload as configured (16 runs x NP 1024, 2000
+    generations), BF16 and FP32 product: per-step time and acceptance over
+    the whole run (one library call, HIP events on the library's stream),
+    median best after 2000 generations next to the FP64 oracle's (stored by
+    tests/golden/make_c3_reference.py), and the wall time of one de_evolve
+    call until half of the runs reach the oracle's median final best (the
+    time to the (n/2)-th run's first hit, from the call's wall time per
+    generation).  With with_oracle, the oracle's time to the same point is
+    extrapolated from one timed generation of all 16 runs on the host
+    cores."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2405_16551_amd import instances
+    from paper_2405_16551_amd.de import DifferentialEvolution
+
+    with open(os.path.join(ROOT, "tests", "golden",
+                           "oracle_c3_distribution.json")) as f:
+        ref = json.load(f)
+    c = ref["config"]
+    G = c["G"]
+    o, R = instances.make_instance(c["kind"], c["D"], c["obj_seed"])
+    trials = c["runs"] * c["NP"]
+
+    def make(prec):
+        return DifferentialEvolution(runs=c["runs"], NP=c["NP"], D=c["D"],
+                                     F=c["F"], CR=c["CR"], seed=c["seed"],
+                                     kind=c["kind"], o=o, R=R, gemm_prec=prec)
+
+    out = dict(workload=(f"DE/rand/1/bin, {c['runs']} runs x NP={c['NP']}, "
+                         f"D={c['D']}, rotated oscillating, {G} generations"),
+               oracle_median_best=float(np.median(ref["best"][str(G)])))
+    for prec in ("bf16", "fp32"):
+        de = make(prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(de.stream)
+        de.generation(G)
+        e1.record(de.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        acc, best = de.stats()
+        out[prec] = dict(ms_per_step=round(ms / G, 5),
+                         run_seconds=round(ms * 1e-3, 4),
+                         accept_rate=round(sum(acc) / float(trials * G), 4),
+                         median_best=float(np.median(best)))
+        de.close()
+    # wall time to the oracle's median final best (BF16 product)
+    target = ref["median_final_best"]
+    de = make("bf16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, hits = de.evolve(max_gens, target=target, check_every=check_every)
+    t = time.perf_counter() - t0
+    de.close()
+    h = np.sort(np.array([x if x >= 0 else np.inf for x in hits], float))
+    gmed = float(h[(len(h) + 1) // 2 - 1])
+    ohits = np.sort(np.array([x if x >= 0 else np.inf
+                              for x in ref["oracle_first_gen_at_target"]],
+                             float))
+    omed = float(ohits[(len(ohits) + 1) // 2 - 1])
+    tt = dict(target=target,
+              target_source=("median over the runs of the FP64 oracle's best "
+                             f"after {G} generations (same seeds and instance)"),
+              generations_run=done, seconds=round(t, 4),
+              check_every=check_every,
+              runs_at_target=int(np.isfinite(h).sum()),
+              generation_half_at_target=(gmed if np.isfinite(gmed) else None),
+              seconds_to_half_at_target=(round(gmed * t / done, 4)
+                                         if np.isfinite(gmed) else None))
+    if with_oracle:
+        threads = oracle.max_threads()
+        pop = oracle.init_population(c["runs"], c["NP"], c["D"], c["lo"],
+                                     c["hi"], c["seed"])
+        fit = oracle.objective_batch(oracle.OBJ_ROT_OSC,
+                                     pop.reshape(-1, c["D"]), o, R,
+                                     nthreads=threads).reshape(c["runs"], -1)
+        t1 = time.perf_counter()
+        oracle.generation(pop, fit, F=c["F"], CR=c["CR"], lo=c["lo"],
+                          hi=c["hi"], seed=c["seed"], gen=0,
+                          kind=oracle.OBJ_ROT_OSC, o=o, R=R, nthreads=threads)
+        per_gen = time.perf_counter() - t1
+        tt["oracle"] = dict(
+            generation_half_at_target=omed, cores=threads,
+            seconds_per_generation=round(per_gen, 3),
+            seconds_to_half_at_target=round(omed * per_gen, 1),
+            sample=f"1 generation of all {c['runs']} runs in FP64, "
+                   "extrapolated")
+    out["time_to_target"] = tt
+    return out
+
+
 def cpu_baseline(name, budget_s=15.0):
     """The FP64 oracle on the host cores, one generation of one run of the
     workload (NP trials), repeated while the budget lasts."""
@@ -602,6 +700,8 @@ def main():
         line["time_to_target"] = time_to_target()
         line["time_to_target_c2"] = time_to_target_c2(
             with_oracle=not args.no_cpu_baseline)
+        if args.workload == "rot1000_bf16":
+            line["c3_run"] = c3_run(with_oracle=not args.no_cpu_baseline)
         line["copy_ceiling"] = copy_ceiling()
         line["gemm_ceiling"] = gemm_ceiling()
     if not args.no_cpu_baseline:

@@ -102,7 +102,9 @@ def test_batch_generation_matches_oracle(variant):
 @pytest.mark.parametrize("specs", [
     [(64, 200, 0.5, 0.9), (100, 200, 0.5, 0.9), (40, 600, 0.6, 0.8)],
     [(64, 100, 0.5, 0.9), (100, 100, 0.7, 0.3), (33, 60, 0.6, 1.0)],
-])
+    [(64, 1000, 0.5, 0.9), (68, 1000, 0.5, 0.9), (100, 500, 0.6, 0.8),
+     (40, 700, 0.7, 0.3)],
+], ids=["wide", "paired", "large"])
 def test_wide_variant_equals_per_problem_handle(specs):
     # the wide variant runs the per-problem BF16 tile with the run's own
     # arguments: run r of a batch equals run r of a de.h handle bit for bit
@@ -110,7 +112,10 @@ def test_wide_variant_equals_per_problem_handle(specs):
     # pads to 640: 1024-thread tiles; one plan, two wide launches).  At
     # padded width 128 (D = 60, 100) the handle builds trials two rows per
     # wave instruction (paired rows) and the batch one row per instruction:
-    # same draws, operations and order, so equal bit for bit as well.
+    # same draws, operations and order, so equal bit for bit as well.  At
+    # padded widths 512, 768 and 1024 (D = 500, 700, 1000, the headline
+    # width) with ragged last tiles: NP = 68 leaves a last tile of 4 rows,
+    # so most waves of that tile have no row of their own.
     from paper_2405_16551_amd.de import DE_BATCH_WIDE
     b, inst = make_batch(specs, plan={D: DE_BATCH_WIDE for D in
                                       {s[1] for s in specs}},

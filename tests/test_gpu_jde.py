@@ -49,6 +49,9 @@ def make_jde(**kw):
     # tiles; at padded width 128 the same in the paired-row form
     ("rot_osc", "bf16", 2, 8256, 200),
     ("rot_osc", "bf16", 2, 8256, 100),
+    # padded width 1024 (the headline width); NP = 100 leaves a ragged
+    # last tile
+    ("rot_osc", "bf16", 2, 100, 1000),
 ])
 def test_jde_generation_matches_oracle(kind, prec, runs, NP, D):
     de, o, R = make_jde(runs=runs, NP=NP, D=D, F=0.5, CR=0.9, seed=3,

@@ -425,6 +425,39 @@ def test_c2_distribution_full_size():
         assert ok, (g, pu, pks)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_c3_distribution_full_size(prec):
+    # 16 runs x NP 1024, D 1000, rotated, 2000 generations (the headline
+    # workload as configured): the GPU's best over the runs at every
+    # checkpoint against the FP64 oracle's stored distribution
+    # (tests/golden/make_c3_reference.py), with the BF16 and the FP32
+    # rotation product
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "oracle_c3_distribution.json")) as f:
+        gold = json.load(f)
+    c = gold["config"]
+    de, o, R = make_de(runs=c["runs"], NP=c["NP"], D=c["D"], F=c["F"],
+                       CR=c["CR"], seed=c["seed"], kind=c["kind"],
+                       gemm_prec=prec)
+    done = 0
+    for g in gold["checkpoints"]:
+        de.generation(g - done)
+        done = g
+        gpu = np.array(de.stats()[1])
+        ok, pu, pks = de_stats.same_distribution(gpu, gold["best"][str(g)])
+        print(f"c3 {prec} gen {g}: gpu median {np.median(gpu):.4e} oracle "
+              f"median {np.median(gold['best'][str(g)]):.4e} p_U {pu:.3f} "
+              f"p_KS {pks:.3f}", flush=True)
+        assert ok, (g, pu, pks)
+    acc, _ = de.stats()
+    rate = sum(acc) / (c["runs"] * c["NP"] * c["G"])
+    orate = sum(gold["accepted"]) / (c["runs"] * c["NP"] * c["G"])
+    print(f"c3 {prec} acceptance over the run: gpu {rate:.4f} oracle "
+          f"{orate:.4f}")
+    assert abs(rate - orate) <= 0.1 * orate
+
+
 # ---------------------------------------------------------------------------
 # Full-size workloads (16 runs x NP 1024 x D 1000, the benchmark's launch
 # configuration): every row of a generation against the oracle, early (the

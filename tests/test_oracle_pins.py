@@ -485,6 +485,39 @@ def test_c2_distribution_fixture_prefix():
         gold["best"][str(c["G"])])
 
 
+def test_c3_distribution_fixture_prefix():
+    # the stored 16-run distribution of the headline workload
+    # (tests/golden/make_c3_reference.py) is the oracle's own: the first two
+    # runs' first checkpoint is reproduced bit for bit (a run's draws depend
+    # only on its run number), every stored trace is monotone and agrees
+    # with the checkpoints, and the stored medians fall checkpoint by
+    # checkpoint
+    import json
+    with open(os.path.join(HERE, "golden", "oracle_c3_distribution.json")) as f:
+        gold = json.load(f)
+    c = gold["config"]
+    o, R = instances.make_instance(c["kind"], c["D"], c["obj_seed"])
+    g0 = gold["checkpoints"][0]
+    res = oracle.run(runs=2, NP=c["NP"], D=c["D"], F=c["F"], CR=c["CR"],
+                     lo=c["lo"], hi=c["hi"], seed=c["seed"], kind=1, o=o,
+                     R=R, G=g0, nthreads=8)
+    assert [float(v) for v in res["best_trace"][:, g0]] == \
+        gold["best"][str(g0)][:2]
+    every = gold["trace_every"]
+    for r in range(c["runs"]):
+        tr = gold["trace"][r]
+        assert all(b <= a for a, b in zip(tr, tr[1:]))
+        for g in gold["checkpoints"]:
+            assert tr[g // every] == gold["best"][str(g)][r]
+        h = gold["oracle_first_gen_at_target"][r]
+        if h >= 0:
+            assert tr[-1] <= gold["median_final_best"]
+    med = [np.median(gold["best"][str(g)]) for g in gold["checkpoints"]]
+    assert all(b < a for a, b in zip(med, med[1:]))
+    assert gold["median_final_best"] == np.median(gold["best"][str(c["G"])])
+    assert all(0 < a <= c["NP"] * c["G"] for a in gold["accepted"])
+
+
 # --------------------------------------------------------------------------
 # jDE (control parameters adapted per individual; Section 2's list of DE
 # variants, Section 8.2).  The adaptation constants come from Brest et al.
