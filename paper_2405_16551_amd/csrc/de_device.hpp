@@ -34,6 +34,17 @@ struct Words4 {
   uint32_t w[4];
 };
 
+// Three-way XOR; on gfx950 one v_bitop3_b32 (truth table 0x96) instead of
+// two v_xor_b32.
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b,
+                                                  uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+  return a ^ b ^ c;
+#endif
+}
+
 // One S-box round: two 32x32->64 products (v_mad_u64_u32 on CDNA), the
 // high halves mixed with the other two counter words and the round key.
 __host__ __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
@@ -41,8 +52,8 @@ __host__ __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1
                                              uint32_t k0, uint32_t k1) {
   const uint64_t pa = (uint64_t)kPhiloxMulA * c0;
   const uint64_t pb = (uint64_t)kPhiloxMulB * c2;
-  const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-  const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+  const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+  const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
   c1 = (uint32_t)pb;
   c3 = (uint32_t)pa;
   c0 = n0;
@@ -121,10 +132,19 @@ __host__ __device__ __forceinline__ Donors pick_donors(uint32_t run, uint32_t ge
 }
 
 // Crossover test of eq. 3 for coordinate j = 4q + b: rand_j = (w >> 8) 2^-24
-// and rand_j <= CR  <=>  (w >> 8) <= floor(CR 2^24) = cr_threshold.
+// and rand_j <= CR  <=>  (w >> 8) <= floor(CR 2^24) = cr_threshold
+// <=>  w <= 256 cr_threshold + 255 (all words when cr_threshold >= 2^24 - 1),
+// one comparison of the whole word.  The limit depends on the threshold
+// only, so loops compute it once.
+__host__ __device__ __forceinline__ uint32_t xover_word_limit(
+    uint32_t cr_threshold) {
+  return cr_threshold >= 0xFFFFFFu ? 0xFFFFFFFFu
+                                   : (cr_threshold << 8) | 0xFFu;
+}
+
 __host__ __device__ __forceinline__ bool take_mutant(uint32_t word, int j, int jrand,
                                             uint32_t cr_threshold) {
-  return (j == jrand) || ((word >> 8) <= cr_threshold);
+  return (j == jrand) | (word <= xover_word_limit(cr_threshold));
 }
 
 // Mutant coordinate of eq. 2 with clamping to the box; NaN passes through.

@@ -410,6 +410,10 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
             }
           }
         }
+        // every gather of the step is issued before any of it is used:
+        // keeps the compiler from sinking a row's loads into the guarded
+        // code that consumes them
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int h = 0; h < RB; ++h) {
           if (k + h >= nrow_w) break;
@@ -429,7 +433,7 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
             const int t = t0 + u;
             if (t >= tq) break;
             const int q = lane + 64 * t, j0 = 4 * q;
-            uint32_t bits = 0;
+            bool tk[4] = {false, false, false, false};
             float4 uu = xv[h][u];
             if (!EVAL) {
               const Words4 w = draw_block(kTagXover, rng_run, a.gen,
@@ -437,14 +441,13 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
                                           a.key_hi);
 #pragma unroll
               for (int b = 0; b < 4; ++b) {
-                const bool tk =
-                    (j0 + b < a.D) &&
-                    take_mutant(w.w[b], j0 + b, jrand, crt);
+                // bitwise &: both tests are lane masks, no branch
+                tk[b] = (j0 + b < a.D) &
+                        take_mutant(w.w[b], j0 + b, jrand, crt);
                 const float mv =
                     mutant_coord(get(v1[h][u], b), get(v2[h][u], b),
                                  get(v3[h][u], b), Fr, a.lo, a.hi);
-                set(uu, b, tk ? mv : get(xv[h][u], b));
-                bits |= (tk ? 1u : 0u) << b;
+                set(uu, b, tk[b] ? mv : get(xv[h][u], b));
               }
             }
             float4 y;
@@ -466,10 +469,18 @@ __device__ __forceinline__ void rot_tile(const GenArgs& a, int run, int row0,
               }
             }
             if (!EVAL) {
-#pragma unroll
-              for (int b = 0; b < 4; ++b) {
-                const unsigned long long m = __ballot((bits >> b) & 1u);
-                if (lane == 0) planes[((size_t)rl * tq + t) * 4 + b] = m;
+              // the four crossover planes of the chunk are the ballots of
+              // the decisions (the compare masks themselves), stored by
+              // lane 0 as two 16-byte writes
+              const unsigned long long m0 = __ballot(tk[0]);
+              const unsigned long long m1 = __ballot(tk[1]);
+              const unsigned long long m2 = __ballot(tk[2]);
+              const unsigned long long m3 = __ballot(tk[3]);
+              if (lane == 0) {
+                ulonglong2* pp = reinterpret_cast<ulonglong2*>(
+                    planes + ((size_t)rl * tq + t) * 4);
+                pp[0] = make_ulonglong2(m0, m1);
+                pp[1] = make_ulonglong2(m2, m3);
               }
             }
           }

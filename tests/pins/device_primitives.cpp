@@ -1,7 +1,7 @@
 // Host build of the GPU library's device primitives (de_device.hpp), so the
 // CPU suite can compare them with the independent FP64 oracle and NumPy.
 // Usage: device_primitives MODE < input; one query per line, one answer per
-// line.  MODE: philox | donors | mask | sin2 | mutant | key | xcd.
+// line.  MODE: philox | donors | mask | xover | sin2 | mutant | key | xcd.
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
@@ -55,6 +55,11 @@ int main(int argc, char** argv) {
       }
       std::printf("%s\n", out.data());
     }
+  } else if (!std::strcmp(mode, "xover")) {
+    // word threshold -> 1 if the crossover test takes the mutant (j != jrand)
+    unsigned w, thr;
+    while (std::scanf("%u %u", &w, &thr) == 2)
+      std::printf("%d\n", de::take_mutant(w, 0, 1, thr) ? 1 : 0);
   } else if (!std::strcmp(mode, "sin2")) {
     unsigned b;
     while (std::scanf("%u", &b) == 1)

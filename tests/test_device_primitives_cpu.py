@@ -74,10 +74,27 @@ def test_donors_match_oracle(prim):
         assert tuple(int(v) for v in ln.split()) == oracle.draw_indices(*t)
 
 
+def test_crossover_word_test_is_the_24_bit_comparison(prim):
+    # eq. 3 on the 2^-24 lattice: take the mutant iff (w >> 8) <= threshold;
+    # the library compares the whole word with 256 threshold + 255, so check
+    # words on both sides of every boundary, thresholds up to 2^24 (CR = 1)
+    rng = np.random.default_rng(8)
+    lines, want = [], []
+    for thr in (0, 1, 2, 1 << 23, (1 << 24) - 2, (1 << 24) - 1, 1 << 24):
+        words = {0, 1, 255, 256, 0xFFFFFFFF, 0xFFFFFF00, 0xFFFFFEFF}
+        for d in (-1, 0, 255, 256):
+            words.add((thr * 256 + d) % 2**32)
+        words.update(int(v) for v in rng.integers(0, 2**32, 64))
+        for w in sorted(words):
+            lines.append(f"{w} {thr}")
+            want.append("1" if (w >> 8) <= thr else "0")
+    assert prim("xover", lines) == want
+
+
 def test_crossover_mask_matches_oracle(prim):
     rng = np.random.default_rng(3)
     lines, want = [], []
-    for CR in (0.0, 0.1, 0.5, 0.9, 1.0):
+    for CR in (0.0, 2**-24, 0.1, 0.5, 0.9, 1 - 2**-24, 1.0):
         thr = math.floor(CR * 2**24)
         for _ in range(8):
             seed, run, gen = 5, int(rng.integers(0, 64)), int(rng.integers(0, 10**6))
