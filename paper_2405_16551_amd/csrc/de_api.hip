@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <mutex>
@@ -127,6 +128,15 @@ struct de_state {
   // first de_evolve call, released by de_destroy
   unsigned int* poll_slot;
   hipEvent_t poll_ev[2];
+  // staggered run groups (see run_staggered): two streams and their events,
+  // created on first use, released by de_destroy; the last measured time
+  // per generation (0: none yet) and the generations timed by t0..t1 whose
+  // result has not been read (0: none)
+  hipStream_t grp[2];
+  hipEvent_t grp_fork, grp_join[2], grp_t0, grp_t1;
+  int64_t grp_timed;
+  float gen_us;
+  bool grp_failed;
 };
 
 namespace {
@@ -262,7 +272,131 @@ float f_of_key(unsigned long long key) {
 // Generations per launch of the resident separable form.
 constexpr int64_t kResidentChunk = 1024;
 
+// Staggered run groups, for rotated-objective problems that fill the GPU
+// (at least as many tiles as compute units) with two or more runs.  Every
+// CU of one launch goes through the same phases at the same time: the
+// trial build (Philox draws, gathers of population rows from HBM), then
+// the rotation product (MFMA, R fragments from L2), then selection.  Here
+// the runs are split into two halves, each launched on a stream of its
+// own, and the second half starts about half a generation after the first
+// (a delay kernel of half the last measured time per generation), so one
+// half builds trials while the other multiplies: HBM, L2 and the matrix
+// cores are busy together and the chip's power is spread over the
+// generation.  Each run's kernel arguments and draws are those of the
+// single launch (pointers and the draw counter's run offset by the group's
+// first run), so the results are identical.  DE_STAGGER=0 in the
+// environment turns this off.
+bool stagger_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("DE_STAGGER");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+bool stagger_applies(const de_state* s, int64_t n, hipStream_t st) {
+  if (n < 2 || s->kind != de::kObjRotOsc || s->p.runs < 2 || s->grp_failed ||
+      !stagger_enabled())
+    return false;
+  const long long tiles =
+      (long long)s->p.runs * ((s->p.NP + 63) / 64);
+  if (tiles < de::device_cus()) return false;
+  // a stream being captured into a graph gets the plain launches (the
+  // timing read below is not allowed during capture)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess ||
+      cs != hipStreamCaptureStatusNone)
+    return false;
+  return true;
+}
+
+de_status stagger_setup(de_state* s) {
+  if (s->grp[0]) return DE_OK;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = DE_NOTE(hipStreamCreateWithFlags(&s->grp[k], hipStreamNonBlocking));
+  if (e == hipSuccess)
+    e = DE_NOTE(hipEventCreateWithFlags(&s->grp_fork, hipEventDisableTiming));
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = DE_NOTE(
+        hipEventCreateWithFlags(&s->grp_join[k], hipEventDisableTiming));
+  if (e == hipSuccess) e = DE_NOTE(hipEventCreate(&s->grp_t0));
+  if (e == hipSuccess) e = DE_NOTE(hipEventCreate(&s->grp_t1));
+  if (e != hipSuccess) {
+    s->grp_failed = true;  // plain launches from now on
+    return DE_E_DEVICE;
+  }
+  return DE_OK;
+}
+
+// Arguments of generation s->gen for runs [r0, r0 + nr).
+GenArgs group_args(const de_state* s, int r0, int nr) {
+  GenArgs a = base_args(s);
+  const int b = (int)(s->gen & 1);
+  const size_t rows0 = (size_t)r0 * s->p.NP;
+  a.pop_cur = s->pop[b] + rows0 * s->ldx;
+  a.fit_cur = s->fit[b] + rows0;
+  a.pop_next = s->pop[b ^ 1] + rows0 * s->ldx;
+  a.fit_next = s->fit[b ^ 1] + rows0;
+  a.changed += rows0;
+  a.best_key += r0;
+  a.hit_gen += r0;
+  a.accepted += r0;
+  if (a.jde) {
+    a.jp_cur += rows0;
+    a.jp_next += rows0;
+  }
+  a.runs = nr;
+  a.nrows = nr * s->p.NP;
+  a.run_base = (uint32_t)r0;
+  return a;
+}
+
+de_status run_staggered(de_state* s, int64_t n, hipStream_t st) {
+  // the time per generation measured by an earlier call, once complete
+  if (s->grp_timed > 0 && hipEventQuery(s->grp_t1) == hipSuccess) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->grp_t0, s->grp_t1) == hipSuccess &&
+        ms > 0.f)
+      s->gen_us = ms * 1e3f / (float)s->grp_timed;
+    s->grp_timed = 0;
+  }
+  de_status rc = FROM_HIP(hipEventRecord(s->grp_fork, st));
+  for (int k = 0; k < 2 && rc == DE_OK; ++k)
+    rc = FROM_HIP(hipStreamWaitEvent(s->grp[k], s->grp_fork, 0));
+  if (rc != DE_OK) return rc;
+  const bool time_it = s->grp_timed == 0;
+  if (time_it) rc = FROM_HIP(hipEventRecord(s->grp_t0, s->grp[0]));
+  if (rc == DE_OK && s->gen_us > 0.f)
+    rc = FROM_HIP(de::launch_delay((uint32_t)(s->gen_us * 500.f), s->grp[1]));
+  const int half = s->p.runs / 2;
+  for (int64_t k = 0; k < n && rc == DE_OK; ++k) {
+    rc = FROM_HIP(de::launch_generation(group_args(s, 0, half), s->kind,
+                                        s->prec, s->grp[0]));
+    if (rc == DE_OK)
+      rc = FROM_HIP(de::launch_generation(
+          group_args(s, half, s->p.runs - half), s->kind, s->prec,
+          s->grp[1]));
+    if (rc == DE_OK) s->gen += 1;
+  }
+  if (rc == DE_OK && time_it) {
+    rc = FROM_HIP(hipEventRecord(s->grp_t1, s->grp[0]));
+    if (rc == DE_OK) s->grp_timed = n;
+  }
+  // the caller's stream waits for both halves (also after a failure, so
+  // that nothing launched so far outlives the call's ordering)
+  for (int k = 0; k < 2; ++k) {
+    const de_status r1 = FROM_HIP(hipEventRecord(s->grp_join[k], s->grp[k]));
+    const de_status r2 =
+        r1 == DE_OK ? FROM_HIP(hipStreamWaitEvent(st, s->grp_join[k], 0)) : r1;
+    if (rc == DE_OK) rc = r2;
+  }
+  return rc;
+}
+
 de_status run_generations(de_state* s, int64_t n, hipStream_t st) {
+  if (stagger_applies(s, n, st) && stagger_setup(s) == DE_OK)
+    return run_staggered(s, n, st);
   // small separable problems: several generations per launch, each run's
   // population resident in LDS (results equal the per-generation kernel's)
   if (n >= 2 && s->kind == de::kObjSphere && !s->jde &&
@@ -835,6 +969,15 @@ DE_API de_status de_destroy(de_state* state) {
   for (int k = 0; k < 2; ++k)
     if (state->poll_ev[k]) (void)hipEventDestroy(state->poll_ev[k]);
   if (state->poll_slot) (void)hipHostFree(state->poll_slot);
+  for (int k = 0; k < 2; ++k) {
+    if (state->grp[k]) {
+      (void)hipStreamSynchronize(state->grp[k]);
+      (void)hipStreamDestroy(state->grp[k]);
+    }
+    if (state->grp_join[k]) (void)hipEventDestroy(state->grp_join[k]);
+  }
+  for (hipEvent_t e : {state->grp_fork, state->grp_t0, state->grp_t1})
+    if (e) (void)hipEventDestroy(e);
   delete state;
   return DE_OK;
 }

@@ -81,4 +81,12 @@ hipError_t launch_hit_check(const GenArgs& a, unsigned long long target_key,
 hipError_t launch_debug_draws(const GenArgs& a, int* idx4, uint32_t* mask,
                               hipStream_t s);
 
+// One wave that waits `ns` nanoseconds (at most kMaxDelayNs) on the GPU's
+// constant 100 MHz clock, then ends: a stream-ordered start offset.
+constexpr uint32_t kMaxDelayNs = 1000000;
+hipError_t launch_delay(uint32_t ns, hipStream_t s);
+
+// Compute units of the current device.
+int device_cus();
+
 }  // namespace de

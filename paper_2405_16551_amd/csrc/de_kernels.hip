@@ -187,6 +187,15 @@ __global__ __launch_bounds__(256) void k_init(GenArgs a) {
 }
 
 // o -> zero-padded copy; R -> MFMA B-operand layout (zero-padded).
+// Waits on the constant 100 MHz clock (s_memrealtime) for `ticks` ticks;
+// the loop ends once the clock has advanced that far, whatever the shader
+// clock does.
+__global__ __launch_bounds__(64) void k_delay(uint64_t ticks) {
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (__builtin_amdgcn_s_memrealtime() - t0 < ticks)
+    __builtin_amdgcn_s_sleep(2);
+}
+
 __global__ __launch_bounds__(256) void k_prep_shift(const float* o, int D,
                                                     int dpad, float* o_pad) {
   for (int k = blockIdx.x * 256 + threadIdx.x; k < dpad; k += gridDim.x * 256)
@@ -697,26 +706,6 @@ hipError_t launch_rot_t(const GenArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Compute units of the current device (queried once per device and kept
-// in an atomic, so that handles used from several host threads do not race;
-// 256 if the query fails, which only affects the choice of tile width).
-int device_cus() {
-  constexpr int kMaxDevices = 64;
-  static std::atomic<int> known[kMaxDevices];  // 0: not queried yet
-  int dev = 0, n = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
-  if (dev < kMaxDevices) {
-    n = known[dev].load(std::memory_order_relaxed);
-    if (n > 0) return n;
-  }
-  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
-                            dev) != hipSuccess ||
-      n <= 0)
-    return 256;
-  if (dev < kMaxDevices) known[dev].store(n, std::memory_order_relaxed);
-  return n;
-}
-
 template <bool EVAL>
 hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
   const long long tiles = EVAL ? (a.nrows + 63) / 64
@@ -760,6 +749,26 @@ hipError_t launch_rot_e(const GenArgs& a, int prec, hipStream_t s) {
 }
 
 }  // namespace
+
+// Compute units of the current device (queried once per device and kept
+// in an atomic, so that handles used from several host threads do not race;
+// 256 if the query fails, which only affects the choice of tile width).
+int device_cus() {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> known[kMaxDevices];  // 0: not queried yet
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+  if (dev < kMaxDevices) {
+    n = known[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+  }
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess ||
+      n <= 0)
+    return 256;
+  if (dev < kMaxDevices) known[dev].store(n, std::memory_order_relaxed);
+  return n;
+}
 
 // LDS bytes of the rotated kernel: BF16 tiles of 64 rows, FP32 tiles of 32
 // rows (independent of the number of threads).
@@ -832,6 +841,12 @@ hipError_t note_hip(hipError_t e, const char* file, int line) {
                    hipGetErrorName(e), hipGetErrorString(e));
   }
   return e;
+}
+
+hipError_t launch_delay(uint32_t ns, hipStream_t s) {
+  const uint64_t ticks = (std::min(ns, kMaxDelayNs) + 9) / 10;  // 100 MHz
+  hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, s, ticks);
+  return hipGetLastError();
 }
 
 hipError_t launch_generation(const GenArgs& a, int kind, int prec,
