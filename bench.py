@@ -113,6 +113,12 @@ def measured_traffic(kernel_ms, w):
     return None
 
 
+# Generations per timed library call: calls this long take the library's
+# staggered run groups on the large rotated workloads (shorter calls are
+# launched as one group).
+SEG_MIN_GENS = 16
+
+
 def time_workload(name, steps, warmup, seed=1):
     import torch
 
@@ -133,12 +139,13 @@ def time_workload(name, steps, warmup, seed=1):
     de.generation(warmup)
     torch.cuda.synchronize()
     acc0, _ = de.stats()
-    # the K steps are five library calls of about K/5 generations each
-    # (launches back to back on the library's stream); events on that
-    # stream bracket every call, so the average launch duration includes
-    # the gaps between consecutive launches, and the five segments give a
-    # median and a spread
-    nseg = 5 if steps >= 5 else 1
+    # the K steps are library calls of at least SEG_MIN_GENS generations
+    # each, five when K allows (launches back to back on the library's
+    # stream); events on that stream bracket every call, so the average
+    # launch duration includes the gaps between consecutive launches and
+    # each call's start and end, and several segments give a median and a
+    # spread
+    nseg = max(1, min(5, steps // SEG_MIN_GENS))
     cuts = [steps * k // nseg for k in range(nseg + 1)]
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg + 1)]
     torch.cuda.synchronize()

@@ -159,14 +159,15 @@ DE_API de_status de_init_population(const de_params* params,
  * clamping, eq. 3 crossover, greedy selection: the trial replaces the target
  * iff f(trial) < f(target), so ties and NaN keep the target).  Synchronous
  * generations: every donor comes from generation g.  Asynchronous.
- * Rotated problems with two or more runs and at least one 64-row tile per
- * compute unit run as two run groups on two streams the handle creates on
- * first use (ordered after, and waited for by, hip_stream through events;
- * released by de_destroy), the second group offset by half the time per
- * generation measured on an earlier call, so that one group's trial build
- * overlaps the other's rotation product.  The results are identical to one
- * launch per generation; the environment variable DE_STAGGER=0 turns the
- * split off, and so does a hip_stream that is being captured into a graph. */
+ * Calls of at least 16 generations on rotated problems with two or more
+ * runs and at least one 64-row tile per compute unit run as two run groups
+ * on two streams that such handles create at initialisation (ordered after,
+ * and waited for by, hip_stream through events; released by de_destroy),
+ * the second group offset by half the time per generation measured on an
+ * earlier call, so that one group's trial build overlaps the other's
+ * rotation product.  The results are identical to one launch per
+ * generation; the environment variable DE_STAGGER=0 turns the split off,
+ * and so does a hip_stream that is being captured into a graph.          */
 DE_API de_status de_generation(de_state* state, int32_t n_gens, void* hip_stream);
 
 /* Run until every run's best value is <= target or max_gens further

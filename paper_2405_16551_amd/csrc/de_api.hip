@@ -294,20 +294,27 @@ bool stagger_enabled() {
   return on;
 }
 
-bool stagger_applies(const de_state* s, int64_t n, hipStream_t st) {
-  if (n < 2 || s->kind != de::kObjRotOsc || s->p.runs < 2 || s->grp_failed ||
-      !stagger_enabled())
+// Fewest generations per call that take the split: the second group's
+// offset leaves half a generation of it after the first group's last
+// kernel, so short calls keep one launch per generation.
+constexpr int64_t kStaggerMinGens = 16;
+
+// Problems that take the split: rotated objective, two or more runs, at
+// least one 64-row tile per compute unit.  Their handles create the two
+// streams at initialisation.
+bool stagger_shape(const de_state* s) {
+  if (s->kind != de::kObjRotOsc || s->p.runs < 2 || !stagger_enabled())
     return false;
-  const long long tiles =
-      (long long)s->p.runs * ((s->p.NP + 63) / 64);
-  if (tiles < de::device_cus()) return false;
-  // a stream being captured into a graph gets the plain launches (the
-  // timing read below is not allowed during capture)
+  const long long tiles = (long long)s->p.runs * ((s->p.NP + 63) / 64);
+  return tiles >= de::device_cus();
+}
+
+// A stream being captured into a graph gets the plain launches (event
+// queries and timing are not allowed during capture).
+bool capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cs) != hipSuccess ||
-      cs != hipStreamCaptureStatusNone)
-    return false;
-  return true;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess ||
+         cs != hipStreamCaptureStatusNone;
 }
 
 de_status stagger_setup(de_state* s) {
@@ -352,8 +359,8 @@ GenArgs group_args(const de_state* s, int r0, int nr) {
   return a;
 }
 
-de_status run_staggered(de_state* s, int64_t n, hipStream_t st) {
-  // the time per generation measured by an earlier call, once complete
+// Time per generation of an earlier timed call, once its events completed.
+void read_gen_time(de_state* s) {
   if (s->grp_timed > 0 && hipEventQuery(s->grp_t1) == hipSuccess) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s->grp_t0, s->grp_t1) == hipSuccess &&
@@ -361,6 +368,9 @@ de_status run_staggered(de_state* s, int64_t n, hipStream_t st) {
       s->gen_us = ms * 1e3f / (float)s->grp_timed;
     s->grp_timed = 0;
   }
+}
+
+de_status run_staggered(de_state* s, int64_t n, hipStream_t st) {
   de_status rc = FROM_HIP(hipEventRecord(s->grp_fork, st));
   for (int k = 0; k < 2 && rc == DE_OK; ++k)
     rc = FROM_HIP(hipStreamWaitEvent(s->grp[k], s->grp_fork, 0));
@@ -394,9 +404,26 @@ de_status run_staggered(de_state* s, int64_t n, hipStream_t st) {
   return rc;
 }
 
+de_status run_plain(de_state* s, int64_t n, hipStream_t st);
+
 de_status run_generations(de_state* s, int64_t n, hipStream_t st) {
-  if (stagger_applies(s, n, st) && stagger_setup(s) == DE_OK)
-    return run_staggered(s, n, st);
+  if (n > 0 && s->grp[0] && !s->grp_failed && !capturing(st)) {
+    read_gen_time(s);
+    if (n >= kStaggerMinGens) return run_staggered(s, n, st);
+    // a short call: one launch per generation, timed for later offsets
+    const bool time_it = s->grp_timed == 0;
+    de_status rc = time_it ? FROM_HIP(hipEventRecord(s->grp_t0, st)) : DE_OK;
+    if (rc == DE_OK) rc = run_plain(s, n, st);
+    if (rc == DE_OK && time_it) {
+      rc = FROM_HIP(hipEventRecord(s->grp_t1, st));
+      if (rc == DE_OK) s->grp_timed = n;
+    }
+    return rc;
+  }
+  return run_plain(s, n, st);
+}
+
+de_status run_plain(de_state* s, int64_t n, hipStream_t st) {
   // small separable problems: several generations per launch, each run's
   // population resident in LDS (results equal the per-generation kernel's)
   if (n >= 2 && s->kind == de::kObjSphere && !s->jde &&
@@ -567,6 +594,9 @@ de_status init_common(const de_params* params, const de_objective* objective,
     delete s;
     return rc;
   }
+  // the run-group streams of problems that take the split (a failure
+  // leaves the handle on plain launches)
+  if (stagger_shape(s)) (void)stagger_setup(s);
   {
     std::lock_guard<std::mutex> lk(g_live_mu);
     g_live.insert(s);

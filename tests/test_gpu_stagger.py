@@ -38,9 +38,9 @@ import torch
 from tests.gpu_helpers import make_de
 kw = json.loads(sys.argv[2])
 de, _, _ = make_de(F=0.5, CR=0.9, seed=3, **kw)
-de.generation(3)
+de.generation(16)
 torch.cuda.synchronize()
-de.generation(5)
+de.generation(20)
 torch.cuda.synchronize()
 h = hashlib.sha256()
 h.update(de.population().cpu().numpy().tobytes())
@@ -63,12 +63,13 @@ def _gpu():
 def test_staggered_groups_equal_single_launch(name):
     import torch
     kw = CASES[name]
-    # this process: staggered (the first call runs without an offset, the
-    # second with one, once the first call's time per generation is known)
+    # this process: staggered (calls of at least 16 generations; the first
+    # call runs without an offset, the second with one, once the first
+    # call's time per generation is known)
     de, _, _ = make_de(F=0.5, CR=0.9, seed=3, **kw)
-    de.generation(3)
+    de.generation(16)
     torch.cuda.synchronize()
-    de.generation(5)
+    de.generation(20)
     torch.cuda.synchronize()
     h = hashlib.sha256()
     h.update(host(de.population()).tobytes())
