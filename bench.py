@@ -97,10 +97,12 @@ def kernel_sources_sha256():
 
 
 def measured_traffic(kernel_ms, w):
-    """HBM GB/s of the generation kernel: bytes per launch from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a copy of known
-    size), divided by this run's average launch time.  None when the kernel
-    sources changed after the counters were taken."""
+    """HBM GB/s of the generation kernel: bytes per generation from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a copy of
+    known size; the median dispatch times the launches per generation, two
+    when the runs go as two staggered groups), divided by this run's average
+    time per generation.  None when the kernel sources changed after the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -109,7 +111,9 @@ def measured_traffic(kernel_ms, w):
     sha = kernel_sources_sha256()
     for entry in table.values():
         if entry.get("workload") == w and entry.get("source_sha256") == sha:
-            return round(entry["hbm_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9, 1)
+            per_gen = entry.get("hbm_bytes_per_generation",
+                                entry["hbm_bytes_per_launch"])
+            return round(per_gen / (kernel_ms * 1e-3) / 1e9, 1)
     return None
 
 
