@@ -407,6 +407,182 @@ __global__ __launch_bounds__(256) void k_mlp_infer(SurArgs a, const float* X,
   }
 }
 
+// rows_of_block with the lane-dependent choices as bit selects on a
+// per-lane mask held in a vector register (v_bfi_b32) instead of
+// per-step lane masks, which the register-resident kernel has no scalar
+// registers left for.  Same exchanges and additions, same result.
+__device__ __forceinline__ float bsel(uint32_t m, float a, float b) {
+  const uint32_t ia = __builtin_bit_cast(uint32_t, a);
+  const uint32_t ib = __builtin_bit_cast(uint32_t, b);
+  return __builtin_bit_cast(float, (m & ia) | (~m & ib));  // m ? a : b
+}
+
+__device__ __forceinline__ float rows_of_block_vsel(const floatx16& part,
+                                                    int lane) {
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = part[r];
+#pragma unroll
+  for (int m = 16, sh = 4; m >= 2; m >>= 1, --sh) {
+    const uint32_t up = 0u - (((uint32_t)lane >> sh) & 1u);  // all ones if set
+#pragma unroll
+    for (int k = 0; k < m / 2; ++k) {
+      const float send = bsel(up, v[k], v[k + m / 2]);
+      const float keep = bsel(up, v[k + m / 2], v[k]);
+      v[k] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+// MLP inference with the weights held in registers: one workgroup of
+// H / 32 waves per group of row tiles of one run; wave w keeps the BF16
+// fragments of column block w of W1 (KB1 = Dp / 16 K-steps) and of W2
+// (KB2 = H / 16) for the whole launch, so the K loops read only LDS.  Per
+// 64-row tile: the rows go to LDS in BF16 (the next tile's rows are loaded
+// into registers meanwhile), layer 1 writes relu(A W1^T + b1) to LDS,
+// layer 2's epilogue applies relu(. + b2) and w3 and reduces its 32
+// columns per row; the rows' totals add the waves in order, then b3.
+// Same operands and per-block K order as k_mlp_infer; the row totals add
+// the 32-column blocks in another order (block by block instead of two
+// per wave), a difference within FP32 rounding.
+constexpr int kResTiles = 4;  // 64-row tiles per workgroup
+
+template <int KB1, int KB2>
+__global__ __launch_bounds__(512) void k_mlp_infer_res(SurArgs a, const float* X,
+                                                       size_t x_run_stride,
+                                                       int n, int ldx, float* y,
+                                                       size_t y_run_stride,
+                                                       int run0) {
+  constexpr int Dp = KB1 * 16, H = KB2 * 16, NW = H / 32;
+  constexpr int sa = Dp + 8, sh = H + 8;
+  constexpr int kStage = (kInferRows * Dp + 32 * NW * 2 - 1) / (64 * NW);
+  extern __shared__ __align__(16) char smem[];
+  const int run = run0 + (int)blockIdx.y;
+  const int tid = (int)threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int nthr = 64 * NW;
+  __bf16* A = reinterpret_cast<__bf16*>(smem);
+  __bf16* H1 = A + (size_t)kInferRows * sa;
+  float* ypart = reinterpret_cast<float*>(H1 + (size_t)kInferRows * sh);
+  const float* Xr = X + blockIdx.y * x_run_stride;
+  const float* th = a.theta + (size_t)run * a.pstride;
+  const float* b1 = th + (size_t)H * a.D;
+  const float* b2 = b1 + H + (size_t)H * H;
+  const float* w3 = b2 + H;
+  const float b3 = w3[H];
+  const int li = lane % 32, lk = lane / 32;
+  const int col = wave * 32 + li;
+  const float b1c = b1[col], b2c = b2[col], w3c = w3[col];
+  bf16x8 w1r[KB1], w2r[KB2];
+  {
+    const bf16x8* f1 = reinterpret_cast<const bf16x8*>(a.w1f) +
+                       ((size_t)run * NW + wave) * KB1 * 64 + lane;
+    const bf16x8* f2 = reinterpret_cast<const bf16x8*>(a.w2f) +
+                       ((size_t)run * NW + wave) * KB2 * 64 + lane;
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) w1r[kb] = f1[(size_t)kb * 64];
+#pragma unroll
+    for (int kb = 0; kb < KB2; ++kb) w2r[kb] = f2[(size_t)kb * 64];
+  }
+  const int tiles = (n + kInferRows - 1) / kInferRows;
+  const int t0 = (int)blockIdx.x * kResTiles;
+  const int t1 = min(t0 + kResTiles, tiles);
+  // scaled value of element e (row e / Dp, coordinate e % Dp) of tile t
+  auto xval = [&](int t, int e) {
+    const int r = e / Dp, dd = e - r * Dp;
+    const int row = t * kInferRows + r;
+    float v = 0.f;
+    if (r < kInferRows && row < n && dd < a.D)
+      v = fmaf(Xr[(size_t)row * ldx + dd], a.xs_mul, a.xs_add);
+    return v;
+  };
+  // with at most 16 elements per thread, the next tile's rows are loaded
+  // into registers while the current tile is computed
+  // (held as BF16 pairs: the LDS copy is BF16 anyway)
+  constexpr bool kPre = kStage <= 16;
+  static_assert(!kPre || kStage % 2 == 0, "staging pairs");
+  constexpr int kPairs = kPre ? kStage / 2 : 1;
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  bf16x2 stage[kPairs];
+  auto load_stage = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < kPairs; ++u) {
+      bf16x2 p;
+      p[0] = (__bf16)xval(t, tid + (2 * u) * nthr);
+      p[1] = (__bf16)xval(t, tid + (2 * u + 1) * nthr);
+      stage[u] = p;
+    }
+  };
+  if (kPre && t0 < t1) load_stage(t0);
+  const __bf16* ar0 = A + (size_t)li * sa + 8 * lk;
+  const __bf16* ar1 = ar0 + (size_t)32 * sa;
+  const __bf16* hr0 = H1 + (size_t)li * sh + 8 * lk;
+  const __bf16* hr1 = hr0 + (size_t)32 * sh;
+  for (int t = t0; t < t1; ++t) {
+    if constexpr (kPre) {
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int e = tid + u * nthr;
+        const int r = e / Dp, dd = e - r * Dp;
+        if (r < kInferRows) A[r * sa + dd] = stage[u / 2][u % 2];
+      }
+    } else {
+      for (int e = tid; e < kInferRows * Dp; e += nthr) {
+        const int r = e / Dp, dd = e - r * Dp;
+        A[r * sa + dd] = (__bf16)xval(t, e);
+      }
+    }
+    __syncthreads();  // A of tile t complete; H1 and ypart of t - 1 read
+    if (kPre && t + 1 < t1) load_stage(t + 1);
+    floatx16 c0 = {}, c1 = {};
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) {
+      const bf16x8 x0 = *reinterpret_cast<const bf16x8*>(ar0 + 16 * kb);
+      const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(ar1 + 16 * kb);
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, w1r[kb], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, w1r[kb], c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r / 4) + 4 * lk + (r % 4);
+      H1[row * sh + col] = (__bf16)fmaxf(c0[r] + b1c, 0.f);
+      H1[(32 + row) * sh + col] = (__bf16)fmaxf(c1[r] + b1c, 0.f);
+    }
+    __syncthreads();  // H1 complete
+    c0 = floatx16{};
+    c1 = floatx16{};
+#pragma unroll
+    for (int kb = 0; kb < KB2; ++kb) {
+      const bf16x8 h0 = *reinterpret_cast<const bf16x8*>(hr0 + 16 * kb);
+      const bf16x8 h1 = *reinterpret_cast<const bf16x8*>(hr1 + 16 * kb);
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h0, w2r[kb], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h1, w2r[kb], c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      c0[r] = fmaxf(c0[r] + b2c, 0.f) * w3c;
+      c1[r] = fmaxf(c1[r] + b2c, 0.f) * w3c;
+    }
+    const float s0 = rows_of_block_vsel(c0, lane);
+    const float s1 = rows_of_block_vsel(c1, lane);
+    if ((lane & 1) == 0) {
+      const int r = li >> 1;
+      const int row = 8 * (r / 4) + 4 * lk + (r % 4);
+      ypart[wave * kInferRows + row] = s0;
+      ypart[wave * kInferRows + 32 + row] = s1;
+    }
+    __syncthreads();  // ypart complete
+    const int row = t * kInferRows + tid;
+    if (tid < kInferRows && row < n) {
+      float s = b3;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += ypart[w * kInferRows + tid];
+      y[blockIdx.y * y_run_stride + row] = s;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Choice, true evaluation, selection, next generation, archive insert:
 // kEvalRows targets per workgroup.
@@ -1078,6 +1254,54 @@ de_status set_lds_attributes() {
   return DE_OK;
 }
 
+// Inference of n rows per run for nruns runs from run0 (X and y strided by
+// run): the register-resident kernel for padded widths up to 128 and
+// H in {32, 64, 128, 256}, else the general one.
+using InferRes = void (*)(SurArgs, const float*, size_t, int, int, float*,
+                          size_t, int);
+
+template <int KB1>
+InferRes infer_res_for_h(int H) {
+  switch (H) {
+    case 32: return &de::k_mlp_infer_res<KB1, 2>;
+    case 64: return &de::k_mlp_infer_res<KB1, 4>;
+    case 128: return &de::k_mlp_infer_res<KB1, 8>;
+    case 256: return &de::k_mlp_infer_res<KB1, 16>;
+    default: return nullptr;
+  }
+}
+
+InferRes infer_res_kernel(int Dp, int H) {
+  switch (Dp) {
+    case 32: return infer_res_for_h<2>(H);
+    case 64: return infer_res_for_h<4>(H);
+    case 96: return infer_res_for_h<6>(H);
+    case 128: return infer_res_for_h<8>(H);
+    default: return nullptr;
+  }
+}
+
+de_status launch_infer(const SurArgs& a, const float* X, size_t x_stride,
+                       int n, int ldx, float* y, size_t y_stride, int run0,
+                       int nruns, hipStream_t st) {
+  if (const InferRes fn = infer_res_kernel(a.Dp, a.H)) {
+    const int tiles = (n + de::kInferRows - 1) / de::kInferRows;
+    const size_t lds = (size_t)de::kInferRows * (a.Dp + 8) * 2 +
+                       (size_t)de::kInferRows * (a.H + 8) * 2 +
+                       (size_t)(a.H / 32) * de::kInferRows * 4;
+    hipLaunchKernelGGL(fn,
+                       dim3((tiles + de::kResTiles - 1) / de::kResTiles, nruns),
+                       dim3(64 * (a.H / 32)), lds, st, a, X, x_stride, n, ldx,
+                       y, y_stride, run0);
+  } else {
+    hipLaunchKernelGGL(de::k_mlp_infer,
+                       dim3((n + de::kInferRows - 1) / de::kInferRows, nruns),
+                       dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a, X,
+                       x_stride, n, ldx, y, y_stride, run0);
+  }
+  return FROM_HIP(hipGetLastError());
+}
+
 de_status prep_model(de_sur* s, hipStream_t st) {
   const SurArgs a = args_of(s);
   const size_t work = (size_t)a.runs *
@@ -1131,13 +1355,8 @@ de_status one_generation(de_sur* s, hipStream_t st) {
   if (rc != DE_OK) return rc;
   if (a.use_model) {
     const int rows = a.NP * a.k;
-    hipLaunchKernelGGL(de::k_mlp_infer,
-                       dim3((rows + de::kInferRows - 1) / de::kInferRows,
-                            a.runs),
-                       dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a,
-                       (const float*)a.cand, (size_t)rows * a.ldx, rows, a.ldx,
-                       a.pred, (size_t)rows, 0);
-    rc = FROM_HIP(hipGetLastError());
+    rc = launch_infer(a, a.cand, (size_t)rows * a.ldx, rows, a.ldx, a.pred,
+                      (size_t)rows, 0, a.runs, st);
     if (rc != DE_OK) return rc;
   }
   hipLaunchKernelGGL(de::k_sur_select,
@@ -1347,11 +1566,7 @@ DE_API de_status de_sur_predict(de_sur* s, int32_t run, const float* x_dev,
   (void)hipGetLastError();
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const SurArgs a = args_of(s);
-  hipLaunchKernelGGL(de::k_mlp_infer,
-                     dim3((n + de::kInferRows - 1) / de::kInferRows, 1),
-                     dim3(256), de::infer_lds_bytes(a.Dp, a.H), st, a, x_dev,
-                     (size_t)0, n, ldx, y_dev, (size_t)0, run);
-  return FROM_HIP(hipGetLastError());
+  return launch_infer(a, x_dev, 0, n, ldx, y_dev, 0, run, 1, st);
 }
 
 DE_API de_status de_sur_get_model(de_sur* s, void* hip_stream, float* theta,
