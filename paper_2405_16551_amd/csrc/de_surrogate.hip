@@ -773,17 +773,78 @@ __device__ __forceinline__ floatx16 mfma_block(const float* ap, int astep,
   return c;
 }
 
+// The same block product with the K extent known at compile time (KS
+// K-steps of 2): the B values of the first 64 K-steps are requested before
+// the first MFMA and each later one 64 steps ahead of its use, so the chain
+// waits for about one L2 round trip instead of one per batch of eight
+// K-steps.  Same products and order as mfma_block.
+template <int KS>
+__device__ __forceinline__ floatx16 mfma_block_k(const float* ap, int astep,
+                                                 const float* bbase, int boff,
+                                                 int bstep, int kvalid,
+                                                 int lk) {
+  static_assert(KS % 8 == 0, "K-steps in groups of eight");
+  constexpr int P = KS < 64 ? KS : 64;  // B values in flight
+  float bv[KS];
+  // bbase is the same in every lane (a scalar base per K-step), boff the
+  // lane's offset: B(k, n) at bbase[k * bstep + boff]
+  auto load_b = [&](int u) {
+    const float* row = bbase + (size_t)2 * u * bstep;
+    return 2 * u + lk < kvalid ? row[boff] : 0.f;
+  };
+#pragma unroll
+  for (int u = 0; u < P; ++u) bv[u] = load_b(u);
+  floatx16 c = {};
+#pragma unroll
+  for (int u0 = 0; u0 < KS; u0 += 8) {
+    // A values of eight K-steps from LDS, their MFMAs, then the B values
+    // P steps ahead; the barrier keeps the scheduler from hoisting every
+    // read of the chain
+    float av[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) av[u] = ap[(size_t)2 * (u0 + u) * astep];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u0 + u], c, 0, 0, 0);
+#pragma unroll
+    for (int u = u0; u < u0 + 8; ++u)
+      if (u + P < KS) bv[u + P] = load_b(u + P);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return c;
+}
+
+// Block product over K (a multiple of 16): the compile-time form when KS
+// is set (KS = K / 2), else the batched one.
+// B(k, n) at bbase[k * bstep + boff] (bbase uniform across the wave).
+template <int KS>
+__device__ __forceinline__ floatx16 train_block(const float* ap, int astep,
+                                                const float* bbase, int boff,
+                                                int bstep, int K, int kvalid,
+                                                int lk) {
+  if constexpr (KS > 0) {
+    return mfma_block_k<KS>(ap, astep, bbase, boff, bstep, kvalid, lk);
+  } else {
+    return mfma_block(ap, astep, bbase + boff, bstep, K, kvalid, lk);
+  }
+}
+
 // Forward pass of 32 minibatch rows per workgroup (8 waves, one 32-column
 // block each per product), output error e = 2 (y - t) / B, delta2 =
 // [h2 > 0] e w3 and delta1 = [h1 > 0] (delta2 W2); what the gradient needs
 // goes to the scratch arrays.  Odd LDS row strides keep the A reads
 // conflict-free.
+// KS1 = Dp / 2 and KS2 = H / 2 when the sizes are compile-time (then
+// every B value of a product is requested at once), 0 otherwise.
+template <int KS1, int KS2>
 __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   extern __shared__ __align__(16) float sm[];
   const int run = (int)blockIdx.y;
-  const int tid = (int)threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int tid = (int)threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int li = lane % 32, lk = lane / 32;
-  const int H = a.H, D = a.D, Dp = a.Dp;
+  const int H = KS2 > 0 ? 2 * KS2 : a.H, D = a.D;
+  const int Dp = KS1 > 0 ? 2 * KS1 : a.Dp;
   const int b0 = (int)blockIdx.x * kTrainRows;
   const int sx = Dp + 1, sh = H + 1;
   float* XS = sm;                       // [32][sx]
@@ -821,8 +882,9 @@ __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   const int nblk = H / 32;
   for (int nb = wave; nb < nblk; nb += 8) {  // layer 1: B(k, n) = W1[n][k]
     const int n = nb * 32 + li;
-    const floatx16 c = mfma_block(XS + li * sx + lk, 1, w1t + (size_t)lk * H + n,
-                                  H, Dp, D, lk);
+    const floatx16 c = train_block<KS1>(XS + li * sx + lk, 1,
+                                        w1t + (size_t)nb * 32, lk * H + li, H,
+                                        Dp, D, lk);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = c_row(r, lane);
@@ -834,8 +896,9 @@ __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   __syncthreads();
   for (int nb = wave; nb < nblk; nb += 8) {  // layer 2: B(k, n) = W2[n][k]
     const int n = nb * 32 + li;
-    const floatx16 c = mfma_block(H1 + li * sh + lk, 1, w2t + (size_t)lk * H + n,
-                                  H, H, H, lk);
+    const floatx16 c = train_block<KS2>(H1 + li * sh + lk, 1,
+                                        w2t + (size_t)nb * 32, lk * H + li, H,
+                                        H, H, lk);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = c_row(r, lane);
@@ -870,8 +933,9 @@ __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   __syncthreads();
   for (int nb = wave; nb < nblk; nb += 8) {  // delta1: B(k = i, n = j) = W2[i][j]
     const int n = nb * 32 + li;
-    const floatx16 c = mfma_block(D2 + li * sh + lk, 1, W2 + (size_t)lk * H + n,
-                                  H, H, H, lk);
+    const floatx16 c = train_block<KS2>(D2 + li * sh + lk, 1,
+                                        W2 + (size_t)nb * 32, lk * H + li, H,
+                                        H, H, lk);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = c_row(r, lane);
@@ -1246,7 +1310,8 @@ de_status set_lds_attributes() {
   const void* fns[] = {reinterpret_cast<const void*>(&de::k_comp_eval),
                        reinterpret_cast<const void*>(&de::k_sur_select),
                        reinterpret_cast<const void*>(&de::k_mlp_infer),
-                       reinterpret_cast<const void*>(&de::k_train_fwd)};
+                       reinterpret_cast<const void*>(&de::k_train_fwd<0, 0>),
+                       reinterpret_cast<const void*>(&de::k_train_fwd<64, 128>)};
   for (const void* f : fns) {
     const de_status rc = FROM_HIP(de::set_max_dynamic_lds(f));
     if (rc != DE_OK) return rc;
@@ -1318,8 +1383,16 @@ de_status train_steps(de_sur* s, int n, hipStream_t st) {
     a.c1 = (float)(1.0 - std::pow((double)s->sp.beta1, (double)s->step));
     a.c2 = (float)(1.0 - std::pow((double)s->sp.beta2, (double)s->step));
     const size_t lds = de::train_lds_floats(a.Dp, a.H) * 4;
-    hipLaunchKernelGGL(de::k_train_fwd, dim3(a.B / de::kTrainRows, a.runs),
-                       dim3(512), lds, st, a);
+    // D padded to 128 and H = 256 (the configured model): the form with
+    // every B value requested at once
+    if (a.Dp == 128 && a.H == 256)
+      hipLaunchKernelGGL((de::k_train_fwd<64, 128>),
+                         dim3(a.B / de::kTrainRows, a.runs), dim3(512), lds,
+                         st, a);
+    else
+      hipLaunchKernelGGL((de::k_train_fwd<0, 0>),
+                         dim3(a.B / de::kTrainRows, a.runs), dim3(512), lds,
+                         st, a);
     de_status rc = FROM_HIP(hipGetLastError());
     if (rc != DE_OK) return rc;
     const int nblocks = (a.H / 32) * (a.Dp / 32) + (a.H / 32) * (a.H / 32);
