@@ -108,8 +108,12 @@ __host__ __device__ constexpr size_t bt_lds_bytes(int dpad) {
 //            statistics; then items (row, group) write the next generation
 //            (trial rows recomputed from the stored bits, stale copies of
 //            rejected rows refreshed).
+// Four waves per SIMD (at most 128 registers): the tiles are latency-bound,
+// so more workgroups per CU in the persistent grid pay more than the
+// compiler's unconstrained allocation (143 registers, three waves).
 template <int BM, int NT, bool EVAL>
-__global__ __launch_bounds__(NT) void k_bt_rot(BatchArgs b) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_bt_rot(BatchArgs b) {
   constexpr int kWaves = NT / 64;
   constexpr int kMblk = BM / 32;
   constexpr int kSlots = kWaves / kMblk;
