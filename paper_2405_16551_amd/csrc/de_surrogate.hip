@@ -944,13 +944,22 @@ __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   }
 }
 
+// One Adam step of a parameter from its moments m, v and value th with
+// gradient g: new moments in mv, vv, new value returned.
+__device__ __forceinline__ float adam_math(const SurArgs& a, float m, float v,
+                                           float th, float g, float& mv,
+                                           float& vv) {
+  mv = fmaf(a.beta1, m, (1.0f - a.beta1) * g);
+  vv = fmaf(a.beta2, v, (1.0f - a.beta2) * g * g);
+  return th - a.lr * (mv / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+}
+
 __device__ __forceinline__ float adam_update(const SurArgs& a, size_t at,
                                              float g) {
-  const float mv = fmaf(a.beta1, a.m[at], (1.0f - a.beta1) * g);
-  const float vv = fmaf(a.beta2, a.v[at], (1.0f - a.beta2) * g * g);
+  float mv, vv;
+  const float t = adam_math(a, a.m[at], a.v[at], a.theta[at], g, mv, vv);
   a.m[at] = mv;
   a.v[at] = vv;
-  const float t = a.theta[at] - a.lr * (mv / a.c1) / (sqrtf(vv / a.c2) + a.eps);
   a.theta[at] = t;
   return t;
 }
@@ -967,10 +976,49 @@ __device__ __forceinline__ size_t frag_index(int n, int k, int K) {
 // 32x32 block (W1: delta1^T xs, W2: delta2^T h1), then Adam on each entry.
 __device__ void grad_vec(const SurArgs& a, int run, int t);
 
+// The weight-gradient block product with the minibatch extent known at
+// compile time (KS K-steps of two rows, every row valid): both operands come
+// from memory, and the values of K-step u + P are requested when the MFMAs
+// of K-steps u .. u + 7 have been issued, so the chain waits for about one
+// round trip per P steps instead of one per batch of eight.  Same products
+// and order as mfma_block.
+template <int KS>
+__device__ __forceinline__ floatx16 mfma_block_mm(const float* ap, int astep,
+                                                  const float* bp,
+                                                  int bstep) {
+  static_assert(KS % 8 == 0, "K-steps in groups of eight");
+  constexpr int P = KS < 32 ? KS : 32;  // K-steps in flight
+  float av[KS], bv[KS];
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    av[u] = ap[(size_t)2 * u * astep];
+    bv[u] = bp[(size_t)2 * u * bstep];
+  }
+  floatx16 c = {};
+#pragma unroll
+  for (int u0 = 0; u0 < KS; u0 += 8) {
+#pragma unroll
+    for (int u = u0; u < u0 + 8; ++u)
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], c, 0, 0, 0);
+#pragma unroll
+    for (int u = u0; u < u0 + 8; ++u) {
+      if (u + P < KS) {
+        av[u + P] = ap[(size_t)2 * (u + P) * astep];
+        bv[u + P] = bp[(size_t)2 * (u + P) * bstep];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return c;
+}
+
 // Workgroups 0 .. ceil(blocks / 4) - 1: one wave per 32x32 weight block;
 // the rest: the vector parameters.  Every updated weight is also written to
-// the BF16 inference copy and the FP32 transposed copy.
+// the BF16 inference copy and the FP32 transposed copy.  KS = B / 2 when the
+// minibatch size is compile-time (the deep-prefetch product), else 0.
+template <int KS>
 __global__ __launch_bounds__(256) void k_train_grad(SurArgs a) {
+  __shared__ float tblk[4][32][33];  // one 32x32 block per wave (+1 column)
   const int run = (int)blockIdx.y;
   const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
   const int li = lane % 32, lk = lane / 32;
@@ -993,29 +1041,76 @@ __global__ __launch_bounds__(256) void k_train_grad(SurArgs a) {
   const float* hv = w1 ? a.xsb + (size_t)run * B * Dp : a.h1b + (size_t)run * B * H;
   const int i = ib * 32 + li, j = jb * 32 + li;
   // A(i, b) = delta[b][i], B(b, j) = input[b][j]; B is a multiple of 32
-  const floatx16 c = mfma_block(dl + (size_t)lk * H + i, H,
-                                hv + (size_t)lk * ldh + j, ldh, B, B, lk);
+  floatx16 c;
+  if constexpr (KS > 0)
+    c = mfma_block_mm<KS>(dl + (size_t)lk * H + i, H,
+                          hv + (size_t)lk * ldh + j, ldh);
+  else
+    c = mfma_block(dl + (size_t)lk * H + i, H, hv + (size_t)lk * ldh + j, ldh,
+                   B, B, lk);
+  // Adam on the lane's 16 entries: the entries are distinct, so every m, v
+  // and theta is read before any is written and the reads share one wait
   const size_t base = (size_t)run * a.pstride;
+  const int jj = jb * 32 + li;
+  const bool valid = !w1 || jj < D;
+  float mo[16], vo[16], to[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int ii = ib * 32 + c_row(r, lane), jj = jb * 32 + li;
-    if (w1) {
-      if (jj < D) {
-        const float t = adam_update(a, base + (size_t)ii * D + jj, c[r]);
-        a.w1t[((size_t)run * D + jj) * H + ii] = t;
-        a.w1f[(size_t)run * H * Dp + frag_index(ii, jj, Dp)] = (__bf16)t;
-      }
-    } else {
-      const float t =
-          adam_update(a, base + (size_t)H * D + H + (size_t)ii * H + jj, c[r]);
-      a.w2t[((size_t)run * H + jj) * H + ii] = t;
-      a.w2f[(size_t)run * H * H + frag_index(ii, jj, H)] = (__bf16)t;
+    const int ii = ib * 32 + c_row(r, lane);
+    const size_t at = w1 ? base + (size_t)ii * D + jj
+                         : base + (size_t)H * D + H + (size_t)ii * H + jj;
+    if (valid) {
+      mo[r] = a.m[at];
+      vo[r] = a.v[at];
+      to[r] = a.theta[at];
     }
+  }
+  // the block's new weights (0 in W1's padding columns) go through LDS so
+  // that the transposed copy is written in rows of 32 and the BF16
+  // fragment copy in 16-byte pieces
+  float(*tb)[33] = tblk[wave];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int rr = c_row(r, lane);
+    float t = 0.f;
+    if (valid) {
+      const int ii = ib * 32 + rr;
+      const size_t at = w1 ? base + (size_t)ii * D + jj
+                           : base + (size_t)H * D + H + (size_t)ii * H + jj;
+      float mv, vv;
+      t = adam_math(a, mo[r], vo[r], to[r], c[r], mv, vv);
+      a.m[at] = mv;
+      a.v[at] = vv;
+      a.theta[at] = t;
+    }
+    tb[rr][li] = t;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // transposed copy: row jj of wT holds column jj of the block (32 floats)
+  float* wt = w1 ? a.w1t + (size_t)run * D * H : a.w2t + (size_t)run * H * H;
+  const int nrow_t = w1 ? D : H;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int jl = 2 * s2 + lk, jr = jb * 32 + jl;
+    if (jr < nrow_t) wt[(size_t)jr * H + ib * 32 + li] = tb[li][jl];
+  }
+  // BF16 fragments: K-steps 2 jb and 2 jb + 1 of block row ib, 1 KB each
+  const int K = w1 ? Dp : H;
+  __bf16* wf = (w1 ? a.w1f + (size_t)run * H * Dp : a.w2f + (size_t)run * H * H) +
+               (((size_t)ib * (K / 16) + 2 * jb) * 64 + lane) * 8;
+#pragma unroll
+  for (int kbl = 0; kbl < 2; ++kbl) {
+    bf16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (__bf16)tb[li][kbl * 16 + lk * 8 + q];
+    *reinterpret_cast<bf16x8*>(wf + (size_t)kbl * 64 * 8) = v;
   }
 }
 
 // Bias and output-layer gradients (3H + 1 per run, t indexes them), summed
-// over the minibatch rows, then Adam.
+// over the minibatch rows, then Adam.  Eight partial sums over rows
+// b = u mod 8, each in increasing b, added in order at the end; the rows'
+// values are read 32 at a time so that the reads share one wait.
 __device__ void grad_vec(const SurArgs& a, int run, int t) {
   const int H = a.H, D = a.D, B = a.B;
   if (t > 3 * H) return;
@@ -1023,33 +1118,38 @@ __device__ void grad_vec(const SurArgs& a, int run, int t) {
   const float* d2 = a.d2b + (size_t)run * B * H;
   const float* h2 = a.h2b + (size_t)run * B * H;
   const float* e = a.eb + (size_t)run * B;
-  // eight partial sums over rows b = u mod 8 (independent load chains),
-  // added in order at the end
-  float gp[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // row b contributes col[b * stride] (w3: times e[b])
+  const float* col;
+  int stride = H;
+  bool times_e = false;
   size_t p;
   if (t < H) {  // b1
-    for (int b = 0; b < B; b += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) gp[u] += d1[(size_t)(b + u) * H + t];
+    col = d1 + t;
     p = (size_t)H * D + t;
   } else if (t < 2 * H) {  // b2
-    const int i = t - H;
-    for (int b = 0; b < B; b += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) gp[u] += d2[(size_t)(b + u) * H + i];
-    p = (size_t)H * D + H + (size_t)H * H + i;
+    col = d2 + (t - H);
+    p = (size_t)H * D + H + (size_t)H * H + (t - H);
   } else if (t < 3 * H) {  // w3
-    const int i = t - 2 * H;
-    for (int b = 0; b < B; b += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        gp[u] = fmaf(e[b + u], h2[(size_t)(b + u) * H + i], gp[u]);
-    p = (size_t)H * D + H + (size_t)H * H + H + i;
+    col = h2 + (t - 2 * H);
+    times_e = true;
+    p = (size_t)H * D + H + (size_t)H * H + H + (t - 2 * H);
   } else {  // b3
-    for (int b = 0; b < B; b += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) gp[u] += e[b + u];
+    col = e;
+    stride = 1;
     p = (size_t)H * D + H + (size_t)H * H + 2 * H;
+  }
+  float gp[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  constexpr int kChunk = 32;  // B is a multiple of 32
+  for (int b0 = 0; b0 < B; b0 += kChunk) {
+    float v[kChunk], w[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      v[q] = col[(size_t)(b0 + q) * stride];
+      w[q] = times_e ? e[b0 + q] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q)
+      gp[q % 8] = times_e ? fmaf(w[q], v[q], gp[q % 8]) : gp[q % 8] + v[q];
   }
   float g = 0.f;
 #pragma unroll
@@ -1397,8 +1497,13 @@ de_status train_steps(de_sur* s, int n, hipStream_t st) {
     if (rc != DE_OK) return rc;
     const int nblocks = (a.H / 32) * (a.Dp / 32) + (a.H / 32) * (a.H / 32);
     const int wgs = (nblocks + 3) / 4 + (3 * a.H + 1 + 255) / 256;
-    hipLaunchKernelGGL(de::k_train_grad, dim3(wgs, a.runs), dim3(256), 0, st,
-                       a);
+    // minibatch of 256 (the configured one): the deep-prefetch product
+    if (a.B == 256)
+      hipLaunchKernelGGL((de::k_train_grad<128>), dim3(wgs, a.runs),
+                         dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((de::k_train_grad<0>), dim3(wgs, a.runs), dim3(256),
+                         0, st, a);
     rc = FROM_HIP(hipGetLastError());
     if (rc != DE_OK) return rc;
   }
