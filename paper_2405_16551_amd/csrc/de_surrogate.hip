@@ -688,6 +688,14 @@ __global__ __launch_bounds__(256) void k_model_init(SurArgs a, int P) {
   }
 }
 
+// Position of element (n, k) of a weight matrix with K padded columns in
+// the BF16 MFMA B-operand layout: block n / 32, K-step k / 16, lane, slot.
+__device__ __forceinline__ size_t frag_index(int n, int k, int K) {
+  const size_t nb = n / 32, kb = k / 16;
+  const int ln = (n % 32) + 32 * ((k % 16) / 8);
+  return ((nb * (K / 16) + kb) * 64 + ln) * 8 + (k % 8);
+}
+
 __global__ __launch_bounds__(256) void k_model_prep(SurArgs a) {
   const int H = a.H, D = a.D, Dp = a.Dp;
   const size_t per = (size_t)H * Dp + (size_t)H * H;
@@ -716,10 +724,7 @@ __global__ __launch_bounds__(256) void k_model_prep(SurArgs a) {
       dst = a.w2f + (size_t)run * H * H;
       a.w2t[((size_t)run * H + k) * H + n] = v;
     }
-    // element (n, k) of W -> block n/32, K-step k/16, lane, slot
-    const size_t nb = n / 32, kb = k / 16;
-    const int ln = (n % 32) + 32 * ((k % 16) / 8);
-    dst[((nb * (K / 16) + kb) * 64 + ln) * 8 + (k % 8)] = (__bf16)v;
+    dst[frag_index(n, k, K)] = (__bf16)v;
   }
 }
 
@@ -964,14 +969,6 @@ __device__ __forceinline__ float adam_update(const SurArgs& a, size_t at,
   return t;
 }
 
-// Position of element (n, k) of a weight matrix with K padded columns in
-// the BF16 MFMA B-operand layout: block n / 32, K-step k / 16, lane, slot.
-__device__ __forceinline__ size_t frag_index(int n, int k, int K) {
-  const size_t nb = n / 32, kb = k / 16;
-  const int ln = (n % 32) + 32 * ((k % 16) / 8);
-  return ((nb * (K / 16) + kb) * 64 + ln) * 8 + (k % 8);
-}
-
 // Weight-matrix gradients as products over the minibatch, one wave per
 // 32x32 block (W1: delta1^T xs, W2: delta2^T h1), then Adam on each entry.
 __device__ void grad_vec(const SurArgs& a, int run, int t);
@@ -1094,16 +1091,18 @@ __global__ __launch_bounds__(256) void k_train_grad(SurArgs a) {
     const int jl = 2 * s2 + lk, jr = jb * 32 + jl;
     if (jr < nrow_t) wt[(size_t)jr * H + ib * 32 + li] = tb[li][jl];
   }
-  // BF16 fragments: K-steps 2 jb and 2 jb + 1 of block row ib, 1 KB each
+  // BF16 fragments: K-steps 2 jb and 2 jb + 1 of block row ib, 1 KB each;
+  // lane l holds the eight consecutive k of one row there
   const int K = w1 ? Dp : H;
-  __bf16* wf = (w1 ? a.w1f + (size_t)run * H * Dp : a.w2f + (size_t)run * H * H) +
-               (((size_t)ib * (K / 16) + 2 * jb) * 64 + lane) * 8;
+  __bf16* wf = w1 ? a.w1f + (size_t)run * H * Dp : a.w2f + (size_t)run * H * H;
 #pragma unroll
   for (int kbl = 0; kbl < 2; ++kbl) {
+    const int k0 = kbl * 16 + lk * 8;
     bf16x8 v;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (__bf16)tb[li][kbl * 16 + lk * 8 + q];
-    *reinterpret_cast<bf16x8*>(wf + (size_t)kbl * 64 * 8) = v;
+    for (int q = 0; q < 8; ++q) v[q] = (__bf16)tb[li][k0 + q];
+    *reinterpret_cast<bf16x8*>(wf + frag_index(ib * 32 + li, jb * 32 + k0, K)) =
+        v;
   }
 }
 
