@@ -1496,9 +1496,12 @@ de_status train_steps(de_sur* s, int n, hipStream_t st) {
     if (rc != DE_OK) return rc;
     const int nblocks = (a.H / 32) * (a.Dp / 32) + (a.H / 32) * (a.H / 32);
     const int wgs = (nblocks + 3) / 4 + (3 * a.H + 1 + 255) / 256;
-    // minibatch of 256 (the configured one): the deep-prefetch product
+    // minibatches of 128 and 256: the deep-prefetch product
     if (a.B == 256)
       hipLaunchKernelGGL((de::k_train_grad<128>), dim3(wgs, a.runs),
+                         dim3(256), 0, st, a);
+    else if (a.B == 128)
+      hipLaunchKernelGGL((de::k_train_grad<64>), dim3(wgs, a.runs),
                          dim3(256), 0, st, a);
     else
       hipLaunchKernelGGL((de::k_train_grad<0>), dim3(wgs, a.runs), dim3(256),
