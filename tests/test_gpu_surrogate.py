@@ -127,8 +127,13 @@ def test_model_inference_within_bf16_bound(D, H):
     s.close()
 
 
-def test_adam_step_matches_oracle():
-    D, H, B = 20, 64, 64
+# (20, 64, 64): the general training kernels; (100, 256, 128) and
+# (100, 256, 256): the configured model, whose forward pass has
+# compile-time K extents and whose gradient product requests its operands
+# 32 K-steps ahead (minibatches of 128 and 256)
+@pytest.mark.parametrize("D,H,B", [(20, 64, 64), (100, 256, 128),
+                                   (100, 256, 256)])
+def test_adam_step_matches_oracle(D, H, B):
     s, _ = make_sur(runs=2, NP=64, D=D, hidden=H, batch=B, steps=0,
                     archive=256, model_seed=9)
     s.generation(3)  # archive: 4 rounds of 64 rows
