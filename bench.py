@@ -273,7 +273,7 @@ def describe_surrogate(runs=SUR_RUNS, ncomp=8):
             "1 true evaluation")
 
 
-def time_surrogate(gens=300, check_every=10, runs=SUR_RUNS, ncomp=8,
+def time_surrogate(gens=300, check_every=2, runs=SUR_RUNS, ncomp=8,
                    warm=True, tol=1e-6):
     """Plain form (k = 1, no model, same kernels) for `gens` generations,
     then the surrogate form for up to 2 * gens generations, on the

@@ -728,10 +728,16 @@ __global__ __launch_bounds__(256) void k_model_prep(SurArgs a) {
   }
 }
 
-// Training on FP32 MFMA (32x32x2, lane l supplies A(l % 32, 2 kb + l / 32)
-// and B(2 kb + l / 32, l % 32); register r of lane l holds C(8 (r / 4) +
-// 4 (l / 32) + r % 4, l % 32)).  Minibatch rows in blocks of 32.
-constexpr int kTrainRows = 32;
+// Training on FP32 MFMA.  The gradient's products use 32x32x2 blocks (lane
+// l supplies A(l % 32, 2 kb + l / 32) and B(2 kb + l / 32, l % 32);
+// register r of lane l holds C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32));
+// the forward pass takes the minibatch in blocks of kTrainRows = 16 rows
+// with 16x16x4 blocks (lane l supplies A(l % 16, 4 s + l / 16) and
+// B(4 s + l / 16, l % 16) for K-step s; register r of lane l holds
+// C(4 (l / 16) + r, l % 16)), so that a minibatch of 128 rows of 30 runs
+// already spreads over 240 workgroups.
+constexpr int kTrainRows = 16;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr size_t train_lds_floats(int Dp, int H) {
   return (size_t)kTrainRows * (Dp + 1) + (size_t)3 * kTrainRows * (H + 1) +
@@ -778,85 +784,113 @@ __device__ __forceinline__ floatx16 mfma_block(const float* ap, int astep,
   return c;
 }
 
-// The same block product with the K extent known at compile time (KS
-// K-steps of 2): the B values of the first 64 K-steps are requested before
-// the first MFMA and each later one 64 steps ahead of its use, so the chain
-// waits for about one L2 round trip instead of one per batch of eight
-// K-steps.  Same products and order as mfma_block.
+// Two 16x16 blocks of C = A B over K (a multiple of 32), columns boff0 and
+// boff1 of B, sharing the A reads: the lane's A value of K-step s at
+// ap[4 s + lq] (lq = l / 16), B(k, n) at bb[k * bstep + boff] (rows
+// k >= kvalid read as zero); `two` = 0 leaves c1 untouched.  KS = K / 4 when
+// K is compile-time: the B values of the first 32 K-steps are requested
+// before the first MFMA and each later one 32 steps ahead of its use.
+// Otherwise K-steps go in batches of eight, issued one batch ahead.
 template <int KS>
-__device__ __forceinline__ floatx16 mfma_block_k(const float* ap, int astep,
-                                                 const float* bbase, int boff,
-                                                 int bstep, int kvalid,
-                                                 int lk) {
-  static_assert(KS % 8 == 0, "K-steps in groups of eight");
-  constexpr int P = KS < 64 ? KS : 64;  // B values in flight
-  float bv[KS];
-  // bbase is the same in every lane (a scalar base per K-step), boff the
-  // lane's offset: B(k, n) at bbase[k * bstep + boff]
-  auto load_b = [&](int u) {
-    const float* row = bbase + (size_t)2 * u * bstep;
-    return 2 * u + lk < kvalid ? row[boff] : 0.f;
+__device__ __forceinline__ void mfma16_pair(const float* ap, const float* bb,
+                                            int boff0, int boff1, int bstep,
+                                            int K, int kvalid, int lq,
+                                            bool two, floatx4& c0,
+                                            floatx4& c1) {
+  auto load_b = [&](int st, int boff) {
+    const int k = 4 * st + lq;
+    return k < kvalid ? bb[(size_t)k * bstep + boff] : 0.f;
   };
-#pragma unroll
-  for (int u = 0; u < P; ++u) bv[u] = load_b(u);
-  floatx16 c = {};
-#pragma unroll
-  for (int u0 = 0; u0 < KS; u0 += 8) {
-    // A values of eight K-steps from LDS, their MFMAs, then the B values
-    // P steps ahead; the barrier keeps the scheduler from hoisting every
-    // read of the chain
-    float av[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) av[u] = ap[(size_t)2 * (u0 + u) * astep];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u0 + u], c, 0, 0, 0);
-#pragma unroll
-    for (int u = u0; u < u0 + 8; ++u)
-      if (u + P < KS) bv[u + P] = load_b(u + P);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  return c;
-}
-
-// Block product over K (a multiple of 16): the compile-time form when KS
-// is set (KS = K / 2), else the batched one.
-// B(k, n) at bbase[k * bstep + boff] (bbase uniform across the wave).
-template <int KS>
-__device__ __forceinline__ floatx16 train_block(const float* ap, int astep,
-                                                const float* bbase, int boff,
-                                                int bstep, int K, int kvalid,
-                                                int lk) {
+  c0 = floatx4{0.f, 0.f, 0.f, 0.f};
+  c1 = c0;
   if constexpr (KS > 0) {
-    return mfma_block_k<KS>(ap, astep, bbase, boff, bstep, kvalid, lk);
+    static_assert(KS % 8 == 0, "K-steps in groups of eight");
+    constexpr int P = KS < 32 ? KS : 32;  // K-steps in flight
+    float b0[KS], b1[KS];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      b0[u] = load_b(u, boff0);
+      b1[u] = two ? load_b(u, boff1) : 0.f;
+    }
+#pragma unroll
+    for (int u0 = 0; u0 < KS; u0 += 8) {
+      float av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) av[u] = ap[4 * (u0 + u) + lq];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], b0[u0 + u], c0, 0,
+                                                  0, 0);
+        if (two)
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], b1[u0 + u], c1, 0,
+                                                    0, 0);
+      }
+#pragma unroll
+      for (int u = u0; u < u0 + 8; ++u) {
+        if (u + P < KS) {
+          b0[u + P] = load_b(u + P, boff0);
+          b1[u + P] = two ? load_b(u + P, boff1) : 0.f;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   } else {
-    return mfma_block(ap, astep, bbase + boff, bstep, K, kvalid, lk);
+    float a_n[8], b0n[8], b1n[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a_n[u] = ap[4 * u + lq];
+      b0n[u] = load_b(u, boff0);
+      b1n[u] = two ? load_b(u, boff1) : 0.f;
+    }
+    for (int s0 = 0; s0 < K / 4; s0 += 8) {
+      float ac[8], b0c[8], b1c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        ac[u] = a_n[u];
+        b0c[u] = b0n[u];
+        b1c[u] = b1n[u];
+      }
+      if (s0 + 8 < K / 4) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a_n[u] = ap[4 * (s0 + 8 + u) + lq];
+          b0n[u] = load_b(s0 + 8 + u, boff0);
+          b1n[u] = two ? load_b(s0 + 8 + u, boff1) : 0.f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], b0c[u], c0, 0, 0, 0);
+        if (two)
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], b1c[u], c1, 0, 0,
+                                                    0);
+      }
+    }
   }
 }
 
-// Forward pass of 32 minibatch rows per workgroup (8 waves, one 32-column
-// block each per product), output error e = 2 (y - t) / B, delta2 =
-// [h2 > 0] e w3 and delta1 = [h1 > 0] (delta2 W2); what the gradient needs
-// goes to the scratch arrays.  Odd LDS row strides keep the A reads
-// conflict-free.
-// KS1 = Dp / 2 and KS2 = H / 2 when the sizes are compile-time (then
-// every B value of a product is requested at once), 0 otherwise.
+// Forward pass of 16 minibatch rows per workgroup (8 waves; wave w owns the
+// 16-column blocks w, w + 8, ... of each product, two at a time), output
+// error e = 2 (y - t) / B, delta2 = [h2 > 0] e w3 and delta1 =
+// [h1 > 0] (delta2 W2); what the gradient needs goes to the scratch
+// arrays.  Odd LDS row strides keep the A reads conflict-free.
+// KS1 = Dp / 4 and KS2 = H / 4 when the sizes are compile-time, else 0.
 template <int KS1, int KS2>
 __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
   extern __shared__ __align__(16) float sm[];
   const int run = (int)blockIdx.y;
   const int tid = (int)threadIdx.x, lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
-  const int li = lane % 32, lk = lane / 32;
-  const int H = KS2 > 0 ? 2 * KS2 : a.H, D = a.D;
-  const int Dp = KS1 > 0 ? 2 * KS1 : a.Dp;
+  const int li = lane % 16, lq = lane / 16;
+  const int H = KS2 > 0 ? 4 * KS2 : a.H, D = a.D;
+  const int Dp = KS1 > 0 ? 4 * KS1 : a.Dp;
   const int b0 = (int)blockIdx.x * kTrainRows;
   const int sx = Dp + 1, sh = H + 1;
-  float* XS = sm;                       // [32][sx]
-  float* H1 = XS + kTrainRows * sx;     // [32][sh]
+  float* XS = sm;                       // [16][sx]
+  float* H1 = XS + kTrainRows * sx;     // [16][sh]
   float* H2 = H1 + kTrainRows * sh;
   float* D2 = H2 + kTrainRows * sh;
-  float* E = D2 + kTrainRows * sh;      // [32]
+  float* E = D2 + kTrainRows * sh;      // [16]
   int* src = reinterpret_cast<int*>(E + kTrainRows);
   const float* th = a.theta + (size_t)run * a.pstride;
   const float* b1 = th + (size_t)H * D;
@@ -884,43 +918,52 @@ __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
     a.xsb[(rb + r) * Dp + dd] = v;
   }
   __syncthreads();
-  const int nblk = H / 32;
-  for (int nb = wave; nb < nblk; nb += 8) {  // layer 1: B(k, n) = W1[n][k]
-    const int n = nb * 32 + li;
-    const floatx16 c = train_block<KS1>(XS + li * sx + lk, 1,
-                                        w1t + (size_t)nb * 32, lk * H + li, H,
-                                        Dp, D, lk);
+  const int nblk = H / 16;
+  // the lane's C values: rows 4 lq + r, column li of each block
+  for (int nb = wave; nb < nblk; nb += 16) {  // layer 1: B(k, n) = W1[n][k]
+    const bool two = nb + 8 < nblk;
+    floatx4 c[2];
+    mfma16_pair<KS1>(XS + li * sx, w1t, nb * 16 + li, (nb + 8) * 16 + li, H,
+                     Dp, D, lq, two, c[0], c[1]);
+    for (int q = 0; q < (two ? 2 : 1); ++q) {
+      const int n = (nb + 8 * q) * 16 + li;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = c_row(r, lane);
-      const float v = fmaxf(c[r] + b1[n], 0.f);
-      H1[row * sh + n] = v;
-      a.h1b[(rb + row) * H + n] = v;
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * lq + r;
+        const float v = fmaxf(c[q][r] + b1[n], 0.f);
+        H1[row * sh + n] = v;
+        a.h1b[(rb + row) * H + n] = v;
+      }
     }
   }
   __syncthreads();
-  for (int nb = wave; nb < nblk; nb += 8) {  // layer 2: B(k, n) = W2[n][k]
-    const int n = nb * 32 + li;
-    const floatx16 c = train_block<KS2>(H1 + li * sh + lk, 1,
-                                        w2t + (size_t)nb * 32, lk * H + li, H,
-                                        H, H, lk);
+  for (int nb = wave; nb < nblk; nb += 16) {  // layer 2: B(k, n) = W2[n][k]
+    const bool two = nb + 8 < nblk;
+    floatx4 c[2];
+    mfma16_pair<KS2>(H1 + li * sh, w2t, nb * 16 + li, (nb + 8) * 16 + li, H,
+                     H, H, lq, two, c[0], c[1]);
+    for (int q = 0; q < (two ? 2 : 1); ++q) {
+      const int n = (nb + 8 * q) * 16 + li;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = c_row(r, lane);
-      const float v = fmaxf(c[r] + b2[n], 0.f);
-      H2[row * sh + n] = v;
-      a.h2b[(rb + row) * H + n] = v;
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * lq + r;
+        const float v = fmaxf(c[q][r] + b2[n], 0.f);
+        H2[row * sh + n] = v;
+        a.h2b[(rb + row) * H + n] = v;
+      }
     }
   }
   __syncthreads();
   {
-    const int r = tid / 16, part = tid % 16;
+    // y of row r from 32 partial sums (i = part mod 32), then a butterfly
+    const int r = tid / 32, part = tid % 32;
     float y = 0.f;
-    for (int i = part; i < H; i += 16) y = fmaf(w3[i], H2[r * sh + i], y);
+    for (int i = part; i < H; i += 32) y = fmaf(w3[i], H2[r * sh + i], y);
     y += __shfl_xor(y, 1, 64);
     y += __shfl_xor(y, 2, 64);
     y += __shfl_xor(y, 4, 64);
     y += __shfl_xor(y, 8, 64);
+    y += __shfl_xor(y, 16, 64);
     if (part == 0) {
       const float e =
           2.0f * (y + b3 - a.at[(size_t)run * a.cap + src[r]]) / (float)a.B;
@@ -936,15 +979,18 @@ __global__ __launch_bounds__(512) void k_train_fwd(SurArgs a) {
     a.d2b[(rb + r) * H + i] = dv;
   }
   __syncthreads();
-  for (int nb = wave; nb < nblk; nb += 8) {  // delta1: B(k = i, n = j) = W2[i][j]
-    const int n = nb * 32 + li;
-    const floatx16 c = train_block<KS2>(D2 + li * sh + lk, 1,
-                                        W2 + (size_t)nb * 32, lk * H + li, H,
-                                        H, H, lk);
+  for (int nb = wave; nb < nblk; nb += 16) {  // delta1: B(k = i, n = j) = W2[i][j]
+    const bool two = nb + 8 < nblk;
+    floatx4 c[2];
+    mfma16_pair<KS2>(D2 + li * sh, W2, nb * 16 + li, (nb + 8) * 16 + li, H,
+                     H, H, lq, two, c[0], c[1]);
+    for (int q = 0; q < (two ? 2 : 1); ++q) {
+      const int n = (nb + 8 * q) * 16 + li;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = c_row(r, lane);
-      a.d1b[(rb + row) * H + n] = H1[row * sh + n] > 0.f ? c[r] : 0.f;
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * lq + r;
+        a.d1b[(rb + row) * H + n] = H1[row * sh + n] > 0.f ? c[q][r] : 0.f;
+      }
     }
   }
 }
@@ -1410,7 +1456,7 @@ de_status set_lds_attributes() {
                        reinterpret_cast<const void*>(&de::k_sur_select),
                        reinterpret_cast<const void*>(&de::k_mlp_infer),
                        reinterpret_cast<const void*>(&de::k_train_fwd<0, 0>),
-                       reinterpret_cast<const void*>(&de::k_train_fwd<64, 128>)};
+                       reinterpret_cast<const void*>(&de::k_train_fwd<32, 64>)};
   for (const void* f : fns) {
     const de_status rc = FROM_HIP(de::set_max_dynamic_lds(f));
     if (rc != DE_OK) return rc;
@@ -1485,7 +1531,7 @@ de_status train_steps(de_sur* s, int n, hipStream_t st) {
     // D padded to 128 and H = 256 (the configured model): the form with
     // every B value requested at once
     if (a.Dp == 128 && a.H == 256)
-      hipLaunchKernelGGL((de::k_train_fwd<64, 128>),
+      hipLaunchKernelGGL((de::k_train_fwd<32, 64>),
                          dim3(a.B / de::kTrainRows, a.runs), dim3(512), lds,
                          st, a);
     else
