@@ -108,6 +108,8 @@ def test_debug_draws_bit_exact(runs, NP, D, CR):
     # quads of a row
     ("rot_osc", "fp32", 2, 88, 100, 0.9),
     ("rot_osc", "fp32", 1, 50, 128, 0.5),
+    # the smallest rotated problem: NP = 4, D = 1 (z = +-(x - o))
+    ("rot_osc", "fp32", 2, 4, 1, 0.5),
 ])
 def test_one_generation_matches_oracle(kind, prec, runs, NP, D, CR):
     de, o, R = make_de(runs=runs, NP=NP, D=D, CR=CR, seed=5, kind=kind,
@@ -125,8 +127,13 @@ def test_one_generation_matches_oracle(kind, prec, runs, NP, D, CR):
     res.check(f"{kind}/{prec} {runs}x{NP}x{D} CR={CR}", share=FP32_TIE_SHARE)
 
 
-def test_one_generation_bf16_gemm():
-    runs, NP, D = 2, 70, 100
+# (2, 70, 100): two ragged tiles per run; the smallest problems, NP = 4
+# (three donors and the target) and D = 1 or 2 (one quad of a row, padded
+# to 128 columns of which one or two are live); 65 rows: a last tile of one
+# row
+@pytest.mark.parametrize("runs,NP,D", [(2, 70, 100), (2, 4, 1), (3, 5, 2),
+                                       (1, 65, 33)])
+def test_one_generation_bf16_gemm(runs, NP, D):
     de, o, R = make_de(runs=runs, NP=NP, D=D, seed=5, kind="rot_osc",
                        gemm_prec="bf16")
     de.generation(2)
@@ -138,6 +145,7 @@ def test_one_generation_bf16_gemm():
                              pop32, fit_prev, F=0.5, CR=0.9, seed=5, gen=g,
                              kind=oracle.OBJ_ROT_OSC, o=o, R=R,
                              f_rtol=bf16_rtol(D))
+    assert res.n == runs * NP
     res.check(f"rot_osc/bf16 {runs}x{NP}x{D}")
 
 
