@@ -268,8 +268,8 @@ def describe_surrogate(runs=SUR_RUNS, ncomp=8):
     return (f"surrogate-assisted DE/rand/1/bin, {runs} runs x NP=512, D=100, "
             f"composition of {ncomp} rotated oscillating components (weights "
             "exp(-d/(2*50^2)), biases 100k), F=0.5, CR=0.9; BF16 MLP "
-            "100-256-256-1 trained online (Adam, lr 3e-3, minibatch 128, 1 "
-            "step per generation, archive 16384), k=4 candidates per target, "
+            "100-256-256-1 trained online (Adam, lr 5e-3, minibatch 128, 1 "
+            "step per generation, archive 4096), k=4 candidates per target, "
             "1 true evaluation")
 
 
@@ -298,7 +298,7 @@ def time_surrogate(gens=300, check_every=2, runs=SUR_RUNS, ncomp=8,
 
     comp = instances.make_composition(100, ncomp, 1)
     common = dict(runs=runs, NP=512, D=100, F=0.5, CR=0.9, comp=comp, seed=1,
-                  hidden=256, batch=128, archive=16384, lr=3e-3)
+                  hidden=256, batch=128, archive=4096, lr=5e-3)
     if warm:  # clocks up before anything is timed: a throwaway run of both
         for kw in (dict(k=1, steps=0, warmup_gens=0),
                    dict(k=4, steps=1, warmup_gens=0)):
