@@ -74,8 +74,11 @@ class de_surrogate_params(ctypes.Structure):
                 ("model_seed", ctypes.c_uint64)]
 
 
-SURROGATE_DEFAULTS = dict(k=4, hidden=256, archive=8192, batch=256, steps=2,
-                          warmup_gens=5, lr=1e-3, beta1=0.9, beta2=0.999,
+# The settings measured best on the 100-dimensional composition instances:
+# one Adam step per generation at lr 5e-3 on 128 rows of an archive of the
+# last 4096 evaluations.
+SURROGATE_DEFAULTS = dict(k=4, hidden=256, archive=4096, batch=128, steps=1,
+                          warmup_gens=5, lr=5e-3, beta1=0.9, beta2=0.999,
                           eps=1e-8, model_seed=7)
 
 

@@ -134,8 +134,9 @@ def test_model_inference_within_bf16_bound(D, H):
 @pytest.mark.parametrize("D,H,B", [(20, 64, 64), (100, 256, 128),
                                    (100, 256, 256)])
 def test_adam_step_matches_oracle(D, H, B):
+    lr = 1e-3
     s, _ = make_sur(runs=2, NP=64, D=D, hidden=H, batch=B, steps=0,
-                    archive=256, model_seed=9)
+                    archive=256, model_seed=9, lr=lr)
     s.generation(3)  # archive: 4 rounds of 64 rows
     theta0, m0, v0, t0 = s.get_model()
     assert t0 == 0
@@ -162,7 +163,7 @@ def test_adam_step_matches_oracle(D, H, B):
         # the update is Adam on the GPU's own moments
         mh = m1[run].astype(np.float64) / 0.1
         vh = v1[run].astype(np.float64) / (1 - 0.999)
-        upd = theta0[run] - 1e-3 * mh / (np.sqrt(vh) + 1e-8)
+        upd = theta0[run] - lr * mh / (np.sqrt(vh) + 1e-8)
         np.testing.assert_allclose(theta1[run], upd, rtol=1e-5, atol=1e-8)
     s.close()
 
