@@ -660,7 +660,8 @@ class SurrogateDE:
     """Surrogate-assisted DE on a composition objective (de_surrogate.h).
 
     ``comp``: (O [n, D], R [n, D, D], bias [n], sigma).  ``settings``:
-    overrides of SURROGATE_DEFAULTS.  Populations are views as in
+    overrides of SURROGATE_DEFAULTS (whose archive grows to NP when NP is
+    larger).  Populations are views as in
     DifferentialEvolution; the model state is read and written as NumPy.
     """
 
@@ -682,6 +683,8 @@ class SurrogateDE:
                                    self._O.data_ptr(), self._R.data_ptr(),
                                    self._bias)
         cfg = dict(SURROGATE_DEFAULTS)
+        # the archive holds at least one generation's evaluations
+        cfg["archive"] = max(cfg["archive"], self.NP)
         cfg.update(settings)
         self.cfg = cfg
         self.sp = de_surrogate_params(*[cfg[f] for f, _ in de_surrogate_params._fields_])
