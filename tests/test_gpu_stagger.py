@@ -87,3 +87,51 @@ def test_staggered_groups_equal_single_launch(name):
     ref = json.loads(out.stdout.strip().splitlines()[-1])
     print(name, mine["digest"][:16], ref["digest"][:16], flush=True)
     assert mine == ref
+
+
+EVOLVE_SCRIPT = r"""
+import hashlib, json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from tests.gpu_helpers import make_de
+kw = json.loads(sys.argv[2])
+de, _, _ = make_de(F=0.5, CR=0.9, seed=3, **kw)
+de.generation(int(sys.argv[3]))
+torch.cuda.synchronize()
+h = hashlib.sha256()
+h.update(de.population().cpu().numpy().tobytes())
+h.update(de.fitness().cpu().numpy().tobytes())
+acc, best = de.stats()
+print(json.dumps(dict(digest=h.hexdigest(), acc=list(acc), best=list(best))))
+de.close()
+"""
+
+
+def test_evolve_with_run_groups_equals_plain_generations():
+    # de_evolve in chunks of 32 generations (each chunk a staggered call,
+    # the next chunk enqueued before the previous chunk's flag is read) with
+    # a target no run reaches: the same generations as one unsplit call in
+    # a process with the stagger off
+    import torch
+    kw = CASES["bf16"]
+    gens = 64
+    de, _, _ = make_de(F=0.5, CR=0.9, seed=3, **kw)
+    done, hits = de.evolve(gens, target=-1e30, check_every=32)
+    torch.cuda.synchronize()
+    assert done == gens and all(h < 0 for h in hits)
+    h = hashlib.sha256()
+    h.update(host(de.population()).tobytes())
+    h.update(host(de.fitness()).tobytes())
+    acc, best = de.stats()
+    mine = dict(digest=h.hexdigest(), acc=list(acc), best=list(best))
+    de.close()
+    env = dict(os.environ, DE_STAGGER="0")
+    out = subprocess.run([sys.executable, "-c", EVOLVE_SCRIPT, ROOT,
+                          json.dumps(kw), str(gens)],
+                         env=env, cwd=ROOT, capture_output=True, text=True,
+                         timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    ref = json.loads(out.stdout.strip().splitlines()[-1])
+    print("evolve", mine["digest"][:16], ref["digest"][:16], flush=True)
+    assert mine["digest"] == ref["digest"]
+    assert mine["best"] == ref["best"]
