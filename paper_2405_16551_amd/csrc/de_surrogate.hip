@@ -4,17 +4,20 @@
 // One generation of every run:
 //   k_sur_cand     k DE/rand/1/bin candidates per target (Section 2, eqs. 2
 //                  and 3; candidate c draws with individual field i | c<<24)
-//   k_mlp_infer    the run's MLP D -> H -> H -> 1 on every candidate, BF16
+//   k_mlp_infer_res / k_mlp_infer
+//                  the run's MLP D -> H -> H -> 1 on every candidate, BF16
 //                  32x32x16 MFMA with FP32 accumulation, bias and ReLU
-//                  fused; one workgroup per 32 candidates
+//                  fused; tiles of 64 candidates (the first form, for D
+//                  padded to at most 128, keeps each wave's weight
+//                  fragments in registers over four tiles)
 //   k_sur_select   per target the lowest prediction is evaluated on the
 //                  composition objective (Section 7.3.3 composition
 //                  functions; the expensive step), strict selection, next
 //                  generation, statistics, archive insert
 // then `steps` Adam steps of every run's model (FP32):
 //   k_train_fwd    minibatch rows drawn from the archive, forward pass,
-//                  output error and both hidden-layer deltas, FP32 MFMA
-//                  (32 rows per workgroup)
+//                  output error and both hidden-layer deltas, FP32 16x16x4
+//                  MFMA (16 rows per workgroup)
 //   k_train_grad   weight gradients as FP32 MFMA products over the
 //                  minibatch (one wave per 32x32 block), bias gradients
 //                  from eight partial row sums, then the Adam update per
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(256) void k_sur_cand(SurArgs a) {
 
 // ---------------------------------------------------------------------------
 // MLP inference on MFMA: rows of X (row r at X + r * ldx) of run
-// run0 + blockIdx.y, 32 rows per workgroup of 256 threads.
+// run0 + blockIdx.y, kInferRows rows per workgroup of 256 threads.
 constexpr int kInferRows = 64;
 
 __host__ __device__ constexpr size_t infer_lds_bytes(int Dp, int H) {
