@@ -57,9 +57,10 @@ __device__ __forceinline__ void record_accept(const GenArgs& a, int run, int i,
 //            flight before the crossover draws; trial rows -> LDS A tile as
 //            y = u - o in the GEMM precision, crossover decisions -> bit
 //            planes; padding rows and columns are zero.
-//   phase 2: Z = Y R^T in 32x32 MFMA blocks, wave tile BM x 64 columns, R
-//            fragments prefetched four K-steps ahead from L2; the objective
-//            z^2 + sin^2(3z) is summed per row in registers.
+//   phase 2: Z = Y R^T in 32x32 MFMA blocks, wave tile BM rows x one
+//            32-column block per pass (two for FP32 tiles wider than 256),
+//            R fragments prefetched four K-steps ahead from L2; the
+//            objective z^2 + sin^2(3z) is summed per row in registers.
 //   phase 3: row totals -> selection -> next generation rows (a rejected row
 //            is rewritten only if the other buffer holds a stale copy),
 //            statistics.
